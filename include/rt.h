@@ -1,0 +1,206 @@
+/*
+ * rt.h - C ABI of librtmi, a Whitted ray-tracing render kernel for AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The library renders scenes of spheres and planes lit by point lights:
+ * pinhole primary rays (paper Sections 3.1-3.3), brute-force closest hit
+ * over every primitive (Section 3.4.1), Phong or Blinn-Phong shading
+ * (Section 3.5) with hard cast shadows (Section 3.6), and mirror
+ * reflections up to a fixed bounce limit (Section 3.7).  It also gives the
+ * adjoint of that image with visibility held fixed, and a batched launch of
+ * many scenes.
+ *
+ * Conventions for every call:
+ *   - All calls are C, never throw, and return rt_status.  On failure a
+ *     detail message is available from rt_last_error() (per thread).
+ *   - Argument errors are found on the host before any HIP call and return
+ *     RT_ERR_INVALID_ARG; nothing is launched or written then.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Work is asynchronous on that stream; a device fault surfaces at a later
+ *     call or synchronisation as RT_ERR_DEVICE.
+ *   - Pointers named *_out, records and gradients are caller-owned device
+ *     memory.  rt_scene and rt_batch objects are library-owned and freed by
+ *     their destroy call.
+ *   - Images are row-major, row 0 at the top: element (y, x) of a W x H image
+ *     is at index y * W + x (the paper's pixel index, Section 3.9).
+ *   - Camera frame: x right, y up, the camera looks down -z; yaw turns about
+ *     +y and pitch about +x, pitch applied first.  Pixel (x, y) maps to
+ *     viewport coordinates u = (2x - W) / s, v = (H - 2y) / s, s = min(W, H),
+ *     with no half-pixel offset (Section 3.2 and its worked example); the
+ *     viewport sits at distance 1 / tan(fov / 2) (Section 3.2.1).
+ */
+#ifndef RT_H
+#define RT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RT_MAX_DEPTH 8        /* reflection bounce limit (segments = depth + 1)  */
+#define RT_MAX_LIGHTS 8
+#define RT_MAX_SPHERES 4096
+#define RT_MAX_PLANES 16
+#define RT_MAX_DIM 16384      /* largest W or H                                 */
+#define RT_MAX_BATCH 4096     /* largest number of scenes in one batch          */
+
+typedef enum {
+  RT_OK = 0,
+  RT_ERR_INVALID_ARG = 1,
+  RT_ERR_OUT_OF_MEMORY = 2,
+  RT_ERR_DEVICE = 3,
+  RT_ERR_UNSUPPORTED = 4
+} rt_status;
+
+/* Where the arrays of an rt_scene_desc live. */
+typedef enum { RT_HOST = 0, RT_DEVICE = 1 } rt_mem;
+
+/* Specular model: Blinn's halfway vector (Section 3.5.2, the paper's final
+ * model) or Phong's reflected light vector (the Phong pseudocode of Section
+ * 3.5.1). */
+typedef enum { RT_SPEC_BLINN = 0, RT_SPEC_PHONG = 1 } rt_spec_model;
+
+/* Pinhole camera: the paper's camera[6] argument (Section 3.9): position,
+ * yaw and pitch (degrees), field of view (degrees, 0 < fov < 180) spanning
+ * the shorter image side. */
+typedef struct {
+  float eye[3];
+  float yaw_deg, pitch_deg, fov_deg;
+} rt_camera;
+
+/* Scene description (Section 3.4: every body has a position, a size, a
+ * colour and a reflectivity; the paper's single reflectivity is split into a
+ * specular exponent and a reflection ratio kr used to mix the body colour
+ * with the reflected colour, Section 3.7).  All arrays are float32, packed
+ * row-major with no padding.  Primitive ids: spheres 0..N-1, then planes
+ * N..N+P-1.  With mem == RT_HOST the values are validated on the host; with
+ * RT_DEVICE only counts and pointers are (values are the caller's
+ * responsibility; non-finite values give non-finite pixels). */
+typedef struct {
+  int32_t n_spheres;          /* 0 .. RT_MAX_SPHERES                          */
+  int32_t n_planes;           /* 0 .. RT_MAX_PLANES                           */
+  int32_t n_lights;           /* 0 .. RT_MAX_LIGHTS                           */
+  int32_t spec_model;         /* rt_spec_model                                */
+  const float* sphere_geom;   /* [N][4] centre x y z, radius r (r > 0)        */
+  const float* sphere_mat;    /* [N][4] albedo r g b, reflection ratio kr     */
+  const float* sphere_shine;  /* [N]    specular exponent (> 0)               */
+  const float* plane_geom;    /* [P][4] unit normal m x y z, offset h: m.x = h*/
+  const float* plane_mat;     /* [P][4] albedo r g b, reflection ratio kr     */
+  const float* plane_shine;   /* [P]    specular exponent (> 0)               */
+  const float* light;         /* [L][4] position x y z, intensity I (>= 0)    */
+  float ambient;              /* k_a, share of the colour always visible      */
+  float spec_strength;        /* k_s, scale of the specular term              */
+  float t_min;                /* roots at or below t_min are ignored (>= 0)   */
+  float background[3];        /* colour of a ray that hits nothing            */
+  int32_t mem;                /* rt_mem of the seven arrays above             */
+} rt_scene_desc;
+
+typedef struct rt_scene_s* rt_scene;
+
+/* Per-segment hit records kept by the forward pass for the adjoint
+ * (caller-owned device memory of rt_records_bytes() bytes in total):
+ *   ids: int32 [depth+1][H][W]  primitive hit by segment k, -1 for a miss,
+ *                               -2 for a segment not traced;
+ *   lit: uint8 [depth+1][H][W]  bit l set when light l lit that hit
+ *                               (n.L > 0 and no occluder). */
+typedef struct {
+  int32_t* ids;
+  uint8_t* lit;
+  int64_t bytes;              /* bytes available at ids + lit together        */
+} rt_records;
+
+/* Gradients of a scalar loss (caller-owned device float32, overwritten):
+ * d_albedo [N][3], d_refl [N], d_center [N][3], d_light_pos [L][3],
+ * d_light_int [L].  Any pointer may be NULL to skip that group. */
+typedef struct {
+  float* d_albedo;
+  float* d_refl;
+  float* d_center;
+  float* d_light_pos;
+  float* d_light_int;
+} rt_grads;
+
+/* Copy a scene into library-owned device memory, packed for the kernels
+ * (the paper keeps the scene resident on the device between frames, Section
+ * 2.3).  Allocates; not capture-safe.  Synchronises `stream` before it
+ * returns when mem == RT_HOST. */
+rt_status rt_scene_upload(const rt_scene_desc* desc, void* stream, rt_scene* out);
+
+/* Replace the values of a scene in place (the paper's per-frame stream-in of
+ * camera and body positions, Section 3.9).  Counts and spec_model must
+ * match the uploaded scene.  No allocation; asynchronous on `stream` when
+ * mem == RT_DEVICE. */
+rt_status rt_scene_update(rt_scene scene, const rt_scene_desc* desc, void* stream);
+
+rt_status rt_scene_destroy(rt_scene scene);
+
+/* Bytes of records for a W x H image at the given depth. */
+int64_t rt_records_bytes(int32_t W, int32_t H, int32_t depth);
+
+/* Render one image (the paper's render method, Section 3.9): every pixel
+ * traces its primary ray, shades each hit with shadow rays, and follows
+ * mirror rays up to `depth` bounces (depth 0 = no reflection).
+ *   rgb_out  device float32 [H][W][3], linear colour, not clamped;
+ *   id_out   device int32 [H][W] primary hit id (-1 = miss), or NULL;
+ *   rec      records for rt_render_backward, or NULL.
+ * Launches one kernel; no allocation, capture-safe. */
+rt_status rt_render(rt_scene scene, const rt_camera* cam, int32_t W, int32_t H, int32_t depth,
+                    float* rgb_out, int32_t* id_out, const rt_records* rec, void* stream);
+
+/* Work counters of the render of one image, as the method defines its work
+ * (Sections 3.4.1 and 3.6: every segment tests every primitive; a shadow ray
+ * is traced only when n.L > 0 and tests primitives in ascending id order up
+ * to its first occluder).  Adds to counts (device int64 [5], caller zeroes):
+ * [0] ray-sphere tests, [1] ray-plane tests, [2] primary rays,
+ * [3] reflection rays, [4] shadow rays.  Renders no image; one launch. */
+rt_status rt_render_counts(rt_scene scene, const rt_camera* cam, int32_t W, int32_t H,
+                           int32_t depth, int64_t* counts, void* stream);
+
+/* Adjoint of rt_render with every discrete decision fixed (hit primitive per
+ * segment, lit lights, path length): given dLoss/dRGB (device float32
+ * [H][W][3]) it writes the gradients of the loss with respect to albedo,
+ * reflection ratio and centre of every sphere and position and intensity of
+ * every light.  Radii, exponents, planes, ambient and k_s are constants and
+ * shadow occluders carry no gradient.  With rec == NULL the decisions are
+ * recomputed by re-tracing; otherwise they are read from records written by
+ * rt_render for the same scene, camera, size and depth.  The sum over pixels
+ * is deterministic (fixed order, no floating-point atomics).  No
+ * allocation; capture-safe. */
+rt_status rt_render_backward(rt_scene scene, const rt_camera* cam, int32_t W, int32_t H,
+                             int32_t depth, const float* grad_rgb, const rt_records* rec,
+                             const rt_grads* grads, void* stream);
+
+typedef struct rt_batch_s* rt_batch;
+
+/* Prepare one persistent launch that renders n scenes of any sizes and
+ * depths (each image exactly as rt_render would), captured in a HIP graph.
+ * Builds the tile table (largest estimated cost first), picks the launch
+ * shape (autotuned once per problem signature when `autotune` is non-zero,
+ * which runs and synchronises on `stream`; cached in memory), allocates the
+ * queue counter and captures the graph.  rgb_out[i] is device float32
+ * [H[i]][W[i]][3]. */
+rt_status rt_batch_create(int32_t n, const rt_scene* scenes, const rt_camera* cams,
+                          const int32_t* W, const int32_t* H, const int32_t* depth,
+                          float* const* rgb_out, int32_t autotune, void* stream, rt_batch* out);
+
+/* Replay the batch's graph on `stream`.  Scenes may be updated in place
+ * between launches. */
+rt_status rt_batch_launch(rt_batch batch, void* stream);
+
+/* The same launch without the graph (a plain kernel launch). */
+rt_status rt_batch_launch_direct(rt_batch batch, void* stream);
+
+/* Launch shape chosen for the batch: workgroups and pixel-tile width and
+ * height (any pointer may be NULL). */
+rt_status rt_batch_shape(rt_batch batch, int32_t* workgroups, int32_t* tile_w, int32_t* tile_h);
+
+rt_status rt_batch_destroy(rt_batch batch);
+
+const char* rt_status_string(rt_status status);
+const char* rt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RT_H */

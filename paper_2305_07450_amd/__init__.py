@@ -1,0 +1,307 @@
+"""Python binding of librtmi, the MI355X Whitted ray-tracing library.
+
+Argument marshalling only: every step of rendering and differentiation runs
+in the HIP kernels behind the C ABI declared in include/rt.h.  The functions
+below carry the same names as the C entry points; torch is used for device
+memory and streams.  If librtmi.so is not built the import fails: there is no
+CPU fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, Optional, Sequence
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librtmi.so")
+
+RT_OK, RT_ERR_INVALID_ARG, RT_ERR_OUT_OF_MEMORY, RT_ERR_DEVICE, RT_ERR_UNSUPPORTED = range(5)
+RT_HOST, RT_DEVICE = 0, 1
+RT_SPEC_BLINN, RT_SPEC_PHONG = 0, 1
+RT_MAX_DEPTH = 8
+RT_MAX_LIGHTS = 8
+RT_MAX_SPHERES = 4096
+RT_MAX_PLANES = 16
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is not built: run `python -m paper_2305_07450_amd.build` "
+        "(or __graft_entry__.build()); there is no fallback path")
+
+
+class RtError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_status_name(status)}: {message}")
+        self.status = status
+
+
+class rt_camera(C.Structure):
+    _fields_ = [("eye", C.c_float * 3), ("yaw_deg", C.c_float), ("pitch_deg", C.c_float),
+                ("fov_deg", C.c_float)]
+
+
+class rt_scene_desc(C.Structure):
+    _fields_ = [("n_spheres", C.c_int32), ("n_planes", C.c_int32), ("n_lights", C.c_int32),
+                ("spec_model", C.c_int32),
+                ("sphere_geom", C.c_void_p), ("sphere_mat", C.c_void_p),
+                ("sphere_shine", C.c_void_p), ("plane_geom", C.c_void_p),
+                ("plane_mat", C.c_void_p), ("plane_shine", C.c_void_p), ("light", C.c_void_p),
+                ("ambient", C.c_float), ("spec_strength", C.c_float), ("t_min", C.c_float),
+                ("background", C.c_float * 3), ("mem", C.c_int32)]
+
+
+class rt_records(C.Structure):
+    _fields_ = [("ids", C.c_void_p), ("lit", C.c_void_p), ("bytes", C.c_int64)]
+
+
+class rt_grads(C.Structure):
+    _fields_ = [("d_albedo", C.c_void_p), ("d_refl", C.c_void_p), ("d_center", C.c_void_p),
+                ("d_light_pos", C.c_void_p), ("d_light_int", C.c_void_p)]
+
+
+_lib = C.CDLL(LIB_PATH)
+_vp = C.c_void_p
+_i32 = C.c_int32
+_sig = {
+    "rt_scene_upload": (C.c_int, [C.POINTER(rt_scene_desc), _vp, C.POINTER(_vp)]),
+    "rt_scene_update": (C.c_int, [_vp, C.POINTER(rt_scene_desc), _vp]),
+    "rt_scene_destroy": (C.c_int, [_vp]),
+    "rt_records_bytes": (C.c_int64, [_i32, _i32, _i32]),
+    "rt_render": (C.c_int, [_vp, C.POINTER(rt_camera), _i32, _i32, _i32, _vp, _vp,
+                            C.POINTER(rt_records), _vp]),
+    "rt_render_counts": (C.c_int, [_vp, C.POINTER(rt_camera), _i32, _i32, _i32, _vp, _vp]),
+    "rt_render_backward": (C.c_int, [_vp, C.POINTER(rt_camera), _i32, _i32, _i32, _vp,
+                                     C.POINTER(rt_records), C.POINTER(rt_grads), _vp]),
+    "rt_batch_create": (C.c_int, [_i32, C.POINTER(_vp), C.POINTER(rt_camera), C.POINTER(_i32),
+                                  C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_vp), _i32, _vp,
+                                  C.POINTER(_vp)]),
+    "rt_batch_launch": (C.c_int, [_vp, _vp]),
+    "rt_batch_launch_direct": (C.c_int, [_vp, _vp]),
+    "rt_batch_shape": (C.c_int, [_vp, C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_i32)]),
+    "rt_batch_destroy": (C.c_int, [_vp]),
+    "rt_status_string": (C.c_char_p, [C.c_int]),
+    "rt_last_error": (C.c_char_p, []),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+def _status_name(st: int) -> str:
+    return _lib.rt_status_string(st).decode()
+
+
+def rt_status_string(st: int) -> str:
+    return _status_name(st)
+
+
+def rt_last_error() -> str:
+    return _lib.rt_last_error().decode()
+
+
+def _check(st: int):
+    if st != RT_OK:
+        raise RtError(st, rt_last_error())
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        # the null stream when no GPU is visible (argument checks still run)
+        return torch.cuda.current_stream().cuda_stream if torch.cuda.is_available() else None
+    if isinstance(stream, torch.cuda.Stream):
+        return stream.cuda_stream
+    return int(stream)
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    if isinstance(t, torch.Tensor):
+        return t.data_ptr() if t.numel() else None
+    return t.ctypes.data if t.size else None
+
+
+def make_camera(cam) -> rt_camera:
+    """rt_camera from any object with eye, yaw_deg, pitch_deg, fov_deg."""
+    return rt_camera((C.c_float * 3)(*[float(v) for v in cam.eye]), float(cam.yaw_deg),
+                     float(cam.pitch_deg), float(cam.fov_deg))
+
+
+class _Desc:
+    """rt_scene_desc plus the arrays it points to (kept alive for the call)."""
+
+    def __init__(self, scene, arrays: Optional[Dict[str, object]] = None):
+        get = (lambda k: arrays[k]) if arrays is not None else (lambda k: getattr(scene, k))
+        names = ("sphere_geom", "sphere_mat", "sphere_shine", "plane_geom", "plane_mat",
+                 "plane_shine", "light")
+        vals = [get(k) for k in names]
+        on_dev = [isinstance(v, torch.Tensor) and v.is_cuda for v in vals]
+        if any(on_dev) and not all(on_dev):
+            raise ValueError("scene arrays must be all host or all device arrays")
+        if all(on_dev):
+            vals = [v.detach().to(torch.float32).contiguous() for v in vals]
+            mem = RT_DEVICE
+        else:
+            vals = [np.ascontiguousarray(np.asarray(v, dtype=np.float32)) for v in vals]
+            mem = RT_HOST
+        self.keep = vals
+        n_sph = int(vals[0].shape[0]) if vals[0].ndim else 0
+        n_pl = int(vals[3].shape[0]) if vals[3].ndim else 0
+        n_l = int(vals[6].shape[0]) if vals[6].ndim else 0
+        self.c = rt_scene_desc(
+            n_sph, n_pl, n_l, int(scene.spec_model),
+            *[_ptr(v) for v in vals],
+            float(scene.ambient), float(scene.spec_strength), float(scene.t_min),
+            (C.c_float * 3)(*[float(v) for v in scene.background]), mem)
+
+
+def rt_scene_upload(scene, stream=None, arrays: Optional[Dict[str, object]] = None) -> int:
+    """Upload a scene (numpy arrays -> RT_HOST, CUDA tensors -> RT_DEVICE);
+    returns the opaque rt_scene handle (int)."""
+    d = _Desc(scene, arrays)
+    h = _vp()
+    _check(_lib.rt_scene_upload(C.byref(d.c), _stream(stream), C.byref(h)))
+    return h.value
+
+
+def rt_scene_update(handle: int, scene, stream=None, arrays: Optional[Dict[str, object]] = None):
+    d = _Desc(scene, arrays)
+    _check(_lib.rt_scene_update(handle, C.byref(d.c), _stream(stream)))
+    return d   # caller keeps device arrays alive until the stream has consumed them
+
+
+def rt_scene_destroy(handle: int):
+    _check(_lib.rt_scene_destroy(handle))
+
+
+def rt_records_bytes(W: int, H: int, depth: int) -> int:
+    return int(_lib.rt_records_bytes(W, H, depth))
+
+
+class Records:
+    """Caller-owned device records: ids int32 [depth+1, H, W], lit uint8 [depth+1, H, W]."""
+
+    def __init__(self, W: int, H: int, depth: int, device="cuda"):
+        n = (depth + 1) * H * W
+        self.buf = torch.empty(rt_records_bytes(W, H, depth), dtype=torch.uint8, device=device)
+        self.ids = self.buf[:4 * n].view(torch.int32).view(depth + 1, H, W)
+        self.lit = self.buf[4 * n:].view(depth + 1, H, W)
+        self.c = rt_records(self.ids.data_ptr(), self.lit.data_ptr(), self.buf.numel())
+
+
+def rt_render(handle: int, camera, W: int, H: int, depth: int, rgb_out: torch.Tensor,
+              id_out: Optional[torch.Tensor] = None, rec: Optional[Records] = None,
+              stream=None):
+    cam = make_camera(camera)
+    _check(_lib.rt_render(handle, C.byref(cam), W, H, depth, _ptr(rgb_out), _ptr(id_out),
+                          C.byref(rec.c) if rec is not None else None, _stream(stream)))
+
+
+COUNT_NAMES = ("sphere_tests", "plane_tests", "primary_rays", "reflection_rays", "shadow_rays")
+
+
+def rt_render_counts(handle: int, camera, W: int, H: int, depth: int, counts: torch.Tensor,
+                     stream=None):
+    """Add the algorithmic work counters of one render to counts (int64 [5])."""
+    cam = make_camera(camera)
+    _check(_lib.rt_render_counts(handle, C.byref(cam), W, H, depth, _ptr(counts),
+                                 _stream(stream)))
+
+
+def render_counts(handle: int, camera, W: int, H: int, depth: int) -> Dict[str, int]:
+    c = torch.zeros(5, dtype=torch.int64, device="cuda")
+    rt_render_counts(handle, camera, W, H, depth, c)
+    return dict(zip(COUNT_NAMES, c.cpu().tolist()))
+
+
+def rt_render_backward(handle: int, camera, W: int, H: int, depth: int, grad_rgb: torch.Tensor,
+                       grads: Dict[str, torch.Tensor], rec: Optional[Records] = None,
+                       stream=None):
+    cam = make_camera(camera)
+    g = rt_grads(*[_ptr(grads.get(k)) for k in
+                   ("albedo", "refl", "center", "light_pos", "light_int")])
+    _check(_lib.rt_render_backward(handle, C.byref(cam), W, H, depth, _ptr(grad_rgb),
+                                   C.byref(rec.c) if rec is not None else None, C.byref(g),
+                                   _stream(stream)))
+
+
+def rt_batch_create(handles: Sequence[int], cameras, W: Sequence[int], H: Sequence[int],
+                    depth: Sequence[int], rgb_outs: Sequence[torch.Tensor], autotune: bool = True,
+                    stream=None) -> int:
+    n = len(handles)
+    cams = (rt_camera * n)(*[make_camera(c) for c in cameras])
+    arr = lambda v: (_i32 * n)(*[int(x) for x in v])
+    outs = (_vp * n)(*[_ptr(t) for t in rgb_outs])
+    hs = (_vp * n)(*handles)
+    b = _vp()
+    _check(_lib.rt_batch_create(n, hs, cams, arr(W), arr(H), arr(depth), outs, int(autotune),
+                                _stream(stream), C.byref(b)))
+    return b.value
+
+
+def rt_batch_launch(batch: int, stream=None):
+    _check(_lib.rt_batch_launch(batch, _stream(stream)))
+
+
+def rt_batch_launch_direct(batch: int, stream=None):
+    _check(_lib.rt_batch_launch_direct(batch, _stream(stream)))
+
+
+def rt_batch_shape(batch: int):
+    g, tw, th = _i32(), _i32(), _i32()
+    _check(_lib.rt_batch_shape(batch, C.byref(g), C.byref(tw), C.byref(th)))
+    return g.value, tw.value, th.value
+
+
+def rt_batch_destroy(batch: int):
+    _check(_lib.rt_batch_destroy(batch))
+
+
+# ---------------------------------------------------------------- helpers
+
+class SceneHandle:
+    """Owns one uploaded scene; frees it on close()/garbage collection."""
+
+    def __init__(self, scene, stream=None):
+        self.scene = scene
+        self.handle = rt_scene_upload(scene, stream)
+        self.n_spheres = int(np.asarray(scene.sphere_geom).reshape(-1, 4).shape[0]) \
+            if not isinstance(scene.sphere_geom, torch.Tensor) else int(scene.sphere_geom.shape[0])
+        self.n_lights = int(np.asarray(scene.light).reshape(-1, 4).shape[0]) \
+            if not isinstance(scene.light, torch.Tensor) else int(scene.light.shape[0])
+
+    def close(self):
+        if self.handle:
+            rt_scene_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def render(handle: int, camera, W: int, H: int, depth: int, ids: bool = False,
+           records: bool = False, stream=None, device="cuda"):
+    """Allocate outputs and call rt_render.  Returns (rgb [H,W,3], ids [H,W] or
+    None, Records or None)."""
+    rgb = torch.empty((H, W, 3), dtype=torch.float32, device=device)
+    idt = torch.empty((H, W), dtype=torch.int32, device=device) if ids else None
+    rec = Records(W, H, depth, device) if records else None
+    rt_render(handle, camera, W, H, depth, rgb, idt, rec, stream)
+    return rgb, idt, rec
+
+
+from .autograd import RTRender, render_differentiable  # noqa: E402,F401

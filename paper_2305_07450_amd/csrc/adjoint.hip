@@ -1,0 +1,400 @@
+// adjoint.hip - reverse mode of the render with visibility held fixed.
+//
+// For each pixel the path is replayed from its decisions (primitive hit by
+// each segment and lit-light mask, read from records or recomputed by the
+// same closest-hit and shadow code as the forward pass), giving bit-identical
+// hit points.  The reverse sweep runs over the segments from the last to the
+// first:
+//   C = sum_k T_k (A_k w_k a_k + S_k) [+ T_K bg at a miss],
+//   T_{k+1} = T_k A_k kr_k,  w_k = 1 - kr_k (k < depth), 1 (k = depth),
+//   U_k = dL/dT_k = A_k (w_k g.a_k + kr_k U_{k+1}) + S_k (g_r + g_g + g_b),
+// then through the Blinn/Phong light terms (Section 3.5) into the normal, the
+// hit point and the light, and through p = o + t d, n = (p - c)/r, the root
+// t(o, d, c) (dt/dc = n/(n.d)) and the mirror ray (Section 3.7) into the
+// previous segment's ray.  Shadow occluders, radii, exponents and planes are
+// constants.
+//
+// Summation is deterministic: each wave reduces the contributions of one
+// sphere id with a fixed xor butterfly and adds them into its own LDS
+// accumulator; each workgroup then writes one partial vector, and a second
+// kernel adds the partials in a fixed order.  No floating-point atomics.
+#include "rt_internal.hpp"
+
+namespace rtk {
+
+constexpr int kTileA = 8;
+constexpr int kBlockA = 16;        // pixels per workgroup tile edge (2 x 2 wave tiles)
+constexpr int kLdsFloats = 16384;  // 64 KiB of accumulators per workgroup
+
+__device__ __forceinline__ float wave_sum(float v) {
+  // xor butterfly: every lane ends with the same bits, in a fixed order
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Light terms with a fixed lit mask (no shadow rays): the same arithmetic
+// and order as light_terms() in trace.hpp for the lights that were lit.
+__device__ __forceinline__ void light_terms_fixed(const SceneDev& s, const Surface& f,
+                                                  const Ray& r, uint32_t lit, float& A, float& S) {
+  A = s.ambient;
+  S = 0.0f;
+  for (int l = 0; l < s.n_lights; ++l) {
+    if (!((lit >> l) & 1u)) continue;
+    float4 q = ld4(s.light, l);
+    float lx = q.x - f.px, ly = q.y - f.py, lz = q.z - f.pz;
+    float dist = __builtin_sqrtf(dot3(lx, ly, lz, lx, ly, lz));
+    lx = lx / dist;
+    ly = ly / dist;
+    lz = lz / dist;
+    float nl = dot3(f.nx, f.ny, f.nz, lx, ly, lz);
+    A = fmaf(q.w, nl, A);
+    float x = spec_base(s.spec_model, f.nx, f.ny, f.nz, lx, ly, lz, -r.dx, -r.dy, -r.dz, nl);
+    S = fmaf(q.w * s.spec_strength, spec_pow(x, f.shine), S);
+  }
+}
+
+// Hit distance of a known primitive: the same root the closest-hit search
+// produced for it.
+__device__ __forceinline__ float root_of(const SceneDev& s, const Ray& r, int id) {
+  if (id < s.n_spheres) {
+    float4 g = ld4(s.geom, id);
+    float b;
+    float ff = sphere_ff(g, r, b);
+    return sphere_root(g.w, ff, b, s.t_min);
+  }
+  return plane_root(ld4(s.pgeom, id - s.n_spheres), r, s.t_min);
+}
+
+// Sink that keeps the decisions of a re-traced path in registers.
+struct RegRecords {
+  int ids[kMaxDepth + 1];
+  uint32_t lits[kMaxDepth + 1];
+  __device__ __forceinline__ void seg(int k, int id) {
+    ids[k] = id;
+    lits[k] = 0;
+  }
+  __device__ __forceinline__ void lit(int k, uint32_t m) { lits[k] = m; }
+};
+
+struct V3 {
+  float x, y, z;
+};
+
+__device__ __forceinline__ float dotv(V3 a, V3 b) { return dot3(a.x, a.y, a.z, b.x, b.y, b.z); }
+
+template <bool kHasRecords>
+__global__ __launch_bounds__(256) void adjoint_kernel(SceneDev s, CameraDev c, int depth,
+                                                       const float* __restrict__ grad_rgb,
+                                                       const int32_t* __restrict__ rec_ids,
+                                                       const uint8_t* __restrict__ rec_lit,
+                                                       float* __restrict__ partials, int stride,
+                                                       int n_tiles_x, int n_tiles) {
+  extern __shared__ float acc[];  // [waves][7N] sphere accumulators, then [waves][4L] lights
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int waves = blockDim.x >> 6;
+  const int N = s.n_spheres, L = s.n_lights;
+  const int per_wave = 7 * N;
+  float* my_acc = acc + wave * per_wave;
+  for (int i = threadIdx.x; i < waves * per_wave; i += blockDim.x) acc[i] = 0.0f;
+  __syncthreads();
+
+  float qbar[kMaxLights][3];
+  float ibar[kMaxLights];
+  for (int l = 0; l < kMaxLights; ++l) {
+    qbar[l][0] = qbar[l][1] = qbar[l][2] = 0.0f;
+    ibar[l] = 0.0f;
+  }
+  const int64_t plane = (int64_t)c.W * c.H;
+  // wave tiles of 8 x 8 pixels; a workgroup of `waves` waves covers a strip of
+  // `waves` tiles inside a 16 x 16 block (waves 0..3 -> quadrants)
+  for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+    const int bx = tile % n_tiles_x, by = tile / n_tiles_x;
+    for (int q = wave; q < 4; q += waves) {
+      const int x = bx * kBlockA + (q & 1) * kTileA + (lane & 7);
+      const int y = by * kBlockA + (q >> 1) * kTileA + (lane >> 3);
+      const bool valid = x < c.W && y < c.H;
+      const int64_t pix = valid ? (int64_t)y * c.W + x : 0;
+
+      // decisions of the path
+      RegRecords rr;
+      int K = 0;          // segments with a hit
+      bool ends_in_miss = false;
+      float gr = 0.f, gg = 0.f, gb = 0.f;
+      if (valid) {
+        gr = grad_rgb[3 * pix + 0];
+        gg = grad_rgb[3 * pix + 1];
+        gb = grad_rgb[3 * pix + 2];
+        if (kHasRecords) {
+          for (int k = 0; k <= depth; ++k) {
+            rr.ids[k] = rec_ids[k * plane + pix];
+            rr.lits[k] = rec_lit[k * plane + pix];
+          }
+        } else {
+          for (int k = 0; k <= depth; ++k) rr.ids[k] = kNotTraced;
+          float cr, cg, cb;
+          int prim;
+          trace_path(s, primary_ray(c, x, y), depth, cr, cg, cb, prim, rr);
+        }
+        const int n_prims = s.n_spheres + s.n_planes;
+        for (int k = 0; k <= depth; ++k) {
+          // ids outside the scene (records of another scene) end the path
+          if (rr.ids[k] >= 0 && rr.ids[k] < n_prims) {
+            K = k + 1;
+          } else {
+            ends_in_miss = rr.ids[k] == kMiss;
+            break;
+          }
+        }
+      }
+
+      // forward replay: ray and throughput of every hit segment
+      Ray rays[kMaxDepth + 1];
+      float Ts[kMaxDepth + 1];
+      {
+        Ray r = primary_ray(c, valid ? x : 0, valid ? y : 0);
+        float T = 1.0f;
+        for (int k = 0; k < K; ++k) {
+          rays[k] = r;
+          Ts[k] = T;
+          const int id = rr.ids[k];
+          Surface f = surface_at(s, r, root_of(s, r, id), id);
+          float A, S;
+          light_terms_fixed(s, f, r, rr.lits[k], A, S);
+          if (k < depth) {
+            T = T * (A * f.kr);
+            reflect_ray(r, f);
+          }
+        }
+      }
+
+      // reverse sweep
+      const float gsum = gr + gg + gb;
+      float U = ends_in_miss ? (gr * s.bg_r + gg * s.bg_g + gb * s.bg_b) : 0.0f;
+      V3 obar = {0.f, 0.f, 0.f}, dbar = {0.f, 0.f, 0.f};
+      for (int k = depth; k >= 0; --k) {
+        // every lane runs the same k so that the wave-wide reductions below line up
+        const bool active = valid && k < K;
+        int sid = -1;
+        float sa0 = 0.f, sa1 = 0.f, sa2 = 0.f, skr = 0.f, sc0 = 0.f, sc1 = 0.f, sc2 = 0.f;
+        if (active) {
+          const Ray r = rays[k];
+          const float T = Ts[k];
+          const int id = rr.ids[k];
+          const float t = root_of(s, r, id);
+          Surface f = surface_at(s, r, t, id);
+          float A, S;
+          light_terms_fixed(s, f, r, rr.lits[k], A, S);
+          const float Ga = gr * f.ar + gg * f.ag + gb * f.ab;
+          float Abar, Sbar = T * gsum, krbar = 0.f, wa;
+          if (k < depth) {
+            const float w = 1.0f - f.kr;
+            Abar = T * (w * Ga + f.kr * U);
+            krbar = T * A * (U - Ga);
+            wa = T * A * w;
+            U = A * (w * Ga + f.kr * U) + S * gsum;
+          } else {
+            Abar = T * Ga;
+            wa = T * A;
+            U = A * Ga + S * gsum;
+          }
+          V3 n = {f.nx, f.ny, f.nz}, d = {r.dx, r.dy, r.dz};
+          V3 nbar = {0.f, 0.f, 0.f}, pbar = {0.f, 0.f, 0.f};
+          V3 dloc = {0.f, 0.f, 0.f};  // adjoint of d through the view vector
+          // light terms
+          for (int l = 0; l < L; ++l) {
+            if (!((rr.lits[k] >> l) & 1u)) continue;
+            float4 q = ld4(s.light, l);
+            V3 lv = {q.x - f.px, q.y - f.py, q.z - f.pz};
+            float dist = __builtin_sqrtf(dotv(lv, lv));
+            V3 ld = {lv.x / dist, lv.y / dist, lv.z / dist};
+            float nl = dotv(n, ld);
+            V3 ldbar = {Abar * q.w * n.x, Abar * q.w * n.y, Abar * q.w * n.z};
+            nbar.x += Abar * q.w * ld.x;
+            nbar.y += Abar * q.w * ld.y;
+            nbar.z += Abar * q.w * ld.z;
+            float ibar_l = Abar * nl;
+            float x = spec_base(s.spec_model, n.x, n.y, n.z, ld.x, ld.y, ld.z, -d.x, -d.y, -d.z,
+                                nl);
+            float spec = spec_pow(x, f.shine);
+            ibar_l += Sbar * s.spec_strength * spec;
+            if (x > 0.0f) {
+              float xbar = Sbar * q.w * s.spec_strength * f.shine * spec / x;
+              V3 v = {-d.x, -d.y, -d.z};
+              V3 vbar = {0.f, 0.f, 0.f};
+              if (s.spec_model == 1) {
+                // x = v . (2 nl n - l)
+                V3 rv = {2.f * nl * n.x - ld.x, 2.f * nl * n.y - ld.y, 2.f * nl * n.z - ld.z};
+                vbar = {xbar * rv.x, xbar * rv.y, xbar * rv.z};
+                V3 rbar = {xbar * v.x, xbar * v.y, xbar * v.z};
+                float rn = dotv(rbar, n);
+                nbar.x += 2.f * rn * ld.x + 2.f * nl * rbar.x;
+                nbar.y += 2.f * rn * ld.y + 2.f * nl * rbar.y;
+                nbar.z += 2.f * rn * ld.z + 2.f * nl * rbar.z;
+                ldbar.x += 2.f * rn * n.x - rbar.x;
+                ldbar.y += 2.f * rn * n.y - rbar.y;
+                ldbar.z += 2.f * rn * n.z - rbar.z;
+              } else {
+                // x = n . h / |h|, h = l + v
+                V3 h = {ld.x + v.x, ld.y + v.y, ld.z + v.z};
+                float hl = __builtin_sqrtf(dotv(h, h));
+                V3 hh = {h.x / hl, h.y / hl, h.z / hl};
+                nbar.x += xbar * hh.x;
+                nbar.y += xbar * hh.y;
+                nbar.z += xbar * hh.z;
+                float proj = dotv(hh, n);
+                V3 hbar = {xbar * (n.x - hh.x * proj) / hl, xbar * (n.y - hh.y * proj) / hl,
+                           xbar * (n.z - hh.z * proj) / hl};
+                ldbar.x += hbar.x; ldbar.y += hbar.y; ldbar.z += hbar.z;
+                vbar = hbar;
+              }
+              dloc.x -= vbar.x; dloc.y -= vbar.y; dloc.z -= vbar.z;
+            }
+            // l = lv / |lv|
+            float lp = dotv(ld, ldbar);
+            V3 lvbar = {(ldbar.x - ld.x * lp) / dist, (ldbar.y - ld.y * lp) / dist,
+                        (ldbar.z - ld.z * lp) / dist};
+            qbar[l][0] += lvbar.x; qbar[l][1] += lvbar.y; qbar[l][2] += lvbar.z;
+            ibar[l] += ibar_l;
+            pbar.x -= lvbar.x; pbar.y -= lvbar.y; pbar.z -= lvbar.z;
+          }
+          // mirror ray of this segment feeds segment k+1: o' = p, d' = d - 2 (d.n) n
+          const float dn = dotv(d, n);
+          const float nd1 = dotv(n, dbar);
+          V3 dprev = {dbar.x - 2.f * nd1 * n.x, dbar.y - 2.f * nd1 * n.y,
+                      dbar.z - 2.f * nd1 * n.z};
+          nbar.x -= 2.f * (dn * dbar.x + nd1 * d.x);
+          nbar.y -= 2.f * (dn * dbar.y + nd1 * d.y);
+          nbar.z -= 2.f * (dn * dbar.z + nd1 * d.z);
+          pbar.x += obar.x; pbar.y += obar.y; pbar.z += obar.z;
+          // normal and root
+          V3 cbar = {0.f, 0.f, 0.f};
+          const bool sph = id < s.n_spheres;
+          if (sph) {
+            const float inv_r = ld2(s.rad, id).y;
+            pbar.x += nbar.x * inv_r; pbar.y += nbar.y * inv_r; pbar.z += nbar.z * inv_r;
+            cbar = {-nbar.x * inv_r, -nbar.y * inv_r, -nbar.z * inv_r};
+          }
+          // p = o + t d
+          const float tbar = dotv(pbar, d);
+          V3 onew = pbar;
+          V3 dnew = {dprev.x + dloc.x + t * pbar.x, dprev.y + dloc.y + t * pbar.y,
+                     dprev.z + dloc.z + t * pbar.z};
+          // t(o, d, c): dt = n.(dc - do - t dd) / (n.d)  (plane: m, no dc)
+          const float g = tbar / dn;
+          onew.x -= g * n.x; onew.y -= g * n.y; onew.z -= g * n.z;
+          dnew.x -= g * t * n.x; dnew.y -= g * t * n.y; dnew.z -= g * t * n.z;
+          if (sph) {
+            cbar.x += g * n.x; cbar.y += g * n.y; cbar.z += g * n.z;
+            sid = id;
+            sa0 = wa * gr; sa1 = wa * gg; sa2 = wa * gb;
+            skr = krbar;
+            sc0 = cbar.x; sc1 = cbar.y; sc2 = cbar.z;
+          }
+          obar = onew;
+          dbar = dnew;
+        }
+        // scatter this segment's sphere gradients: one butterfly per distinct id
+        uint64_t pending = __ballot(sid >= 0);
+        while (pending) {
+          const int leader = __builtin_ctzll(pending);
+          const int key = __shfl(sid, leader, 64);
+          const bool mine = sid == key;
+          float v[7] = {sa0, sa1, sa2, skr, sc0, sc1, sc2};
+#pragma unroll
+          for (int j = 0; j < 7; ++j) {
+            float tot = wave_sum(mine ? v[j] : 0.0f);
+            if (lane == 0) my_acc[7 * key + j] += tot;
+          }
+          pending &= ~__ballot(mine);
+        }
+      }
+    }
+  }
+  // light gradients: wave butterfly, then one LDS slot per wave
+  __syncthreads();
+  float* lacc = acc + waves * per_wave;
+  for (int l = 0; l < L; ++l) {
+    float v[4] = {qbar[l][0], qbar[l][1], qbar[l][2], ibar[l]};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      float tot = wave_sum(v[j]);
+      if (lane == 0) lacc[wave * 4 * L + 4 * l + j] = tot;
+    }
+  }
+  __syncthreads();
+  // workgroup partial = waves' accumulators added in wave order
+  float* out = partials + (int64_t)blockIdx.x * stride;
+  for (int i = threadIdx.x; i < per_wave; i += blockDim.x) {
+    float sum = 0.0f;
+    for (int w = 0; w < waves; ++w) sum += acc[w * per_wave + i];
+    out[i] = sum;
+  }
+  for (int i = threadIdx.x; i < 4 * L; i += blockDim.x) {
+    float sum = 0.0f;
+    for (int w = 0; w < waves; ++w) sum += lacc[w * 4 * L + i];
+    out[per_wave + i] = sum;
+  }
+}
+
+// Sum the workgroup partials in block order and scatter to the caller's arrays.
+__global__ void reduce_kernel(const float* __restrict__ partials, int stride, int blocks, int N,
+                              int L, rt_grads g) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= 7 * N + 4 * L) return;
+  float sum = 0.0f;
+  for (int b = 0; b < blocks; ++b) sum += partials[(int64_t)b * stride + j];
+  if (j < 7 * N) {
+    const int i = j / 7, c = j % 7;
+    if (c < 3) {
+      if (g.d_albedo) g.d_albedo[3 * i + c] = sum;
+    } else if (c == 3) {
+      if (g.d_refl) g.d_refl[i] = sum;
+    } else {
+      if (g.d_center) g.d_center[3 * i + (c - 4)] = sum;
+    }
+  } else {
+    const int l = (j - 7 * N) / 4, c = (j - 7 * N) % 4;
+    if (c < 3) {
+      if (g.d_light_pos) g.d_light_pos[3 * l + c] = sum;
+    } else {
+      if (g.d_light_int) g.d_light_int[l] = sum;
+    }
+  }
+}
+
+int adjoint_blocks(int grad_stride);
+
+bool adjoint_supported(int n_spheres) { return 7 * n_spheres + 4 * kMaxLights + 4 <= kLdsFloats; }
+
+hipError_t launch_backward(const rt_scene_s& sc, const CameraDev& c, int depth,
+                           const float* grad_rgb, const int32_t* rec_ids, const uint8_t* rec_lit,
+                           const rt_grads& g, hipStream_t stream) {
+  const int N = sc.n_spheres, L = sc.n_lights;
+  int waves = 4;
+  while (waves > 1 && waves * (7 * N + 4 * L) + 4 > kLdsFloats) --waves;
+  const size_t lds = (size_t)(waves * 7 * N + waves * 4 * L + 4) * sizeof(float);
+  const int n_tiles_x = (c.W + kBlockA - 1) / kBlockA;
+  const int n_tiles = n_tiles_x * ((c.H + kBlockA - 1) / kBlockA);
+  int blocks = adjoint_blocks(sc.grad_stride);
+  if (blocks > n_tiles) blocks = n_tiles;
+  SceneDev s = sc.view();
+  if (rec_ids)
+    hipLaunchKernelGGL(adjoint_kernel<true>, dim3(blocks), dim3(64 * waves), lds, stream, s, c,
+                       depth, grad_rgb, rec_ids, rec_lit, sc.partials, sc.grad_stride, n_tiles_x,
+                       n_tiles);
+  else
+    hipLaunchKernelGGL(adjoint_kernel<false>, dim3(blocks), dim3(64 * waves), lds, stream, s, c,
+                       depth, grad_rgb, rec_ids, rec_lit, sc.partials, sc.grad_stride, n_tiles_x,
+                       n_tiles);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int total = 7 * N + 4 * L;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(reduce_kernel, dim3((total + 255) / 256), dim3(256), 0, stream,
+                     (const float*)sc.partials, sc.grad_stride, blocks, N, L, g);
+  return hipGetLastError();
+}
+
+}  // namespace rtk

@@ -1,0 +1,142 @@
+// render.hip - forward render kernel and scene packing kernel (gfx950).
+//
+// Launch shape: 256-lane workgroups of four wave64s; each wave owns an 8 x 8
+// pixel tile (one lane per pixel, paper Section 3.9: every pixel is an
+// independent work item), so the 64 rays of a wave start from the same eye
+// through neighbouring pixels and take the same branch over most primitives.
+// The scene is read through scalar loads (trace.hpp), so the inner loops are
+// pure VALU arithmetic on SGPR operands.
+#include "rt_internal.hpp"
+
+namespace rtk {
+
+constexpr int kTile = 8;          // wave tile edge
+constexpr int kBlockTiles = 2;    // workgroup = 2 x 2 wave tiles = 16 x 16 pixels
+constexpr int kBlock = kTile * kBlockTiles;
+
+// Records sink: segment ids and lit masks in [depth+1][H][W] planes.
+struct RecordSink {
+  int32_t* id_plane;
+  uint8_t* lit_plane;
+  int64_t plane;
+  int64_t pix;
+  __device__ __forceinline__ void seg(int k, int id) {
+    id_plane[k * plane + pix] = id;
+    if (id < 0) lit_plane[k * plane + pix] = 0;   // a miss has no lit mask
+  }
+  __device__ __forceinline__ void lit(int k, uint32_t m) { lit_plane[k * plane + pix] = (uint8_t)m; }
+};
+
+template <bool kRecords>
+__global__ __launch_bounds__(256) void render_kernel(SceneDev s, CameraDev c, int depth,
+                                                      float* __restrict__ rgb,
+                                                      int32_t* __restrict__ id_out,
+                                                      int32_t* __restrict__ rec_ids,
+                                                      uint8_t* __restrict__ rec_lit) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int x = blockIdx.x * kBlock + (wave & 1) * kTile + (lane & 7);
+  const int y = blockIdx.y * kBlock + (wave >> 1) * kTile + (lane >> 3);
+  if (x >= c.W || y >= c.H) return;
+  const int64_t pix = (int64_t)y * c.W + x;
+  Ray r = primary_ray(c, x, y);
+  float cr, cg, cb;
+  int prim;
+  if (kRecords) {
+    RecordSink sink{rec_ids, rec_lit, (int64_t)c.W * c.H, pix};
+    int traced = trace_path(s, r, depth, cr, cg, cb, prim, sink);
+    for (int k = traced; k <= depth; ++k) {
+      rec_ids[k * sink.plane + pix] = kNotTraced;
+      rec_lit[k * sink.plane + pix] = 0;
+    }
+  } else {
+    NoRecords sink;
+    trace_path(s, r, depth, cr, cg, cb, prim, sink);
+  }
+  rgb[3 * pix + 0] = cr;
+  rgb[3 * pix + 1] = cg;
+  rgb[3 * pix + 2] = cb;
+  if (id_out) id_out[pix] = prim;
+}
+
+// Counting launch: the same paths, plus the algorithmic counters summed per
+// wave (xor butterfly) and added to counts[kNumCounts] with integer atomics.
+__global__ __launch_bounds__(256) void count_kernel(SceneDev s, CameraDev c, int depth,
+                                                    unsigned long long* __restrict__ counts) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int x = blockIdx.x * kBlock + (wave & 1) * kTile + (lane & 7);
+  const int y = blockIdx.y * kBlock + (wave >> 1) * kTile + (lane >> 3);
+  Count cnt;
+  if (x < c.W && y < c.H) {
+    float cr, cg, cb;
+    int prim;
+    NoRecords sink;
+    trace_path(s, primary_ray(c, x, y), depth, cr, cg, cb, prim, sink, cnt);
+  }
+  for (int j = 0; j < kNumCounts; ++j) {
+    int v = cnt.c[j];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) atomicAdd(counts + j, (unsigned long long)v);
+  }
+}
+
+hipError_t launch_counts(const SceneDev& s, const CameraDev& c, int depth,
+                         unsigned long long* counts, hipStream_t stream) {
+  dim3 grid((c.W + kBlock - 1) / kBlock, (c.H + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(count_kernel, grid, dim3(256), 0, stream, s, c, depth, counts);
+  return hipGetLastError();
+}
+
+hipError_t launch_render(const SceneDev& s, const CameraDev& c, int depth, float* rgb,
+                         int32_t* ids, int32_t* rec_ids, uint8_t* rec_lit, hipStream_t stream) {
+  dim3 grid((c.W + kBlock - 1) / kBlock, (c.H + kBlock - 1) / kBlock);
+  if (rec_ids)
+    hipLaunchKernelGGL(render_kernel<true>, grid, dim3(256), 0, stream, s, c, depth, rgb, ids,
+                       rec_ids, rec_lit);
+  else
+    hipLaunchKernelGGL(render_kernel<false>, grid, dim3(256), 0, stream, s, c, depth, rgb, ids,
+                       rec_ids, rec_lit);
+  return hipGetLastError();
+}
+
+// Pack the desc-layout arrays into the kernels' layout: r^2 beside the centre,
+// (r, 1/r), sphere and plane materials in one id-indexed table.
+__global__ void pack_kernel(RawScene raw, int N, int P, int L, float4* geom, float2* rad,
+                            float4* mat, float* shine, float4* pgeom, float4* light) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) {
+    const float* g = raw.sphere_geom + 4 * i;
+    float r = g[3];
+    geom[i] = make_float4(g[0], g[1], g[2], r * r);
+    rad[i] = make_float2(r, 1.0f / r);
+    const float* m = raw.sphere_mat + 4 * i;
+    mat[i] = make_float4(m[0], m[1], m[2], m[3]);
+    shine[i] = raw.sphere_shine[i];
+  }
+  if (i < P) {
+    const float* g = raw.plane_geom + 4 * i;
+    pgeom[i] = make_float4(g[0], g[1], g[2], g[3]);
+    const float* m = raw.plane_mat + 4 * i;
+    mat[N + i] = make_float4(m[0], m[1], m[2], m[3]);
+    shine[N + i] = raw.plane_shine[i];
+  }
+  if (i < L) {
+    const float* q = raw.light + 4 * i;
+    light[i] = make_float4(q[0], q[1], q[2], q[3]);
+  }
+}
+
+hipError_t launch_pack(const rt_scene_s& sc, const RawScene& raw, hipStream_t stream) {
+  int n = sc.n_spheres;
+  if (sc.n_planes > n) n = sc.n_planes;
+  if (sc.n_lights > n) n = sc.n_lights;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(pack_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, raw,
+                     sc.n_spheres, sc.n_planes, sc.n_lights, sc.geom, sc.rad, sc.mat, sc.shine,
+                     sc.pgeom, sc.light);
+  return hipGetLastError();
+}
+
+}  // namespace rtk

@@ -1,0 +1,78 @@
+// rt_internal.hpp - host-side types shared by the C ABI and the launch
+// wrappers of each kernel file.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/rt.h"
+#include "trace.hpp"
+
+// Library-owned scene: one device allocation holding the packed arrays the
+// kernels read, a staging area for host uploads, and the per-workgroup
+// gradient partials of the adjoint.
+struct rt_scene_s {
+  int device = 0;
+  int n_spheres = 0, n_planes = 0, n_lights = 0, spec_model = 0;
+  float ambient = 0, spec_strength = 0, t_min = 0, bg[3] = {0, 0, 0};
+  void* buffer = nullptr;  // single hipMalloc
+  size_t bytes = 0;
+  float4* geom = nullptr;  // [N]   cx cy cz r^2
+  float2* rad = nullptr;   // [N]   r, 1/r
+  float4* mat = nullptr;   // [N+P] albedo, kr
+  float* shine = nullptr;  // [N+P]
+  float4* pgeom = nullptr; // [P]
+  float4* light = nullptr; // [L]
+  float* staging = nullptr;     // raw copy of host desc arrays
+  size_t staging_floats = 0;
+  float* partials = nullptr;    // adjoint partials [kAdjointBlocks][grad_stride]
+  int grad_stride = 0;          // 7N + 4L (padded)
+
+  rtk::SceneDev view() const {
+    rtk::SceneDev s;
+    s.geom = geom; s.rad = rad; s.mat = mat; s.shine = shine; s.pgeom = pgeom; s.light = light;
+    s.n_spheres = n_spheres; s.n_planes = n_planes; s.n_lights = n_lights;
+    s.spec_model = spec_model;
+    s.ambient = ambient; s.spec_strength = spec_strength; s.t_min = t_min;
+    s.bg_r = bg[0]; s.bg_g = bg[1]; s.bg_b = bg[2];
+    return s;
+  }
+};
+
+namespace rtk {
+
+// Workgroups of the persistent adjoint grid (one partial-gradient slot each).
+constexpr int kAdjointBlocks = 1024;
+
+void set_error(const std::string& msg);
+rt_status hip_fail(hipError_t e, const char* what);
+CameraDev camera_dev(const rt_camera& cam, int W, int H);
+
+// Raw (desc-layout) arrays the pack kernel reads.
+struct RawScene {
+  const float* sphere_geom;
+  const float* sphere_mat;
+  const float* sphere_shine;
+  const float* plane_geom;
+  const float* plane_mat;
+  const float* plane_shine;
+  const float* light;
+};
+
+hipError_t launch_pack(const rt_scene_s& sc, const RawScene& raw, hipStream_t stream);
+
+hipError_t launch_render(const SceneDev& s, const CameraDev& c, int depth, float* rgb,
+                         int32_t* ids, int32_t* rec_ids, uint8_t* rec_lit, hipStream_t stream);
+
+hipError_t launch_counts(const SceneDev& s, const CameraDev& c, int depth,
+                         unsigned long long* counts, hipStream_t stream);
+
+bool adjoint_supported(int n_spheres);
+
+hipError_t launch_backward(const rt_scene_s& sc, const CameraDev& c, int depth,
+                           const float* grad_rgb, const int32_t* rec_ids, const uint8_t* rec_lit,
+                           const rt_grads& g, hipStream_t stream);
+
+}  // namespace rtk

@@ -1,0 +1,149 @@
+"""C ABI checks that need no GPU: the library loads, exports every entry
+point that include/rt.h declares, and rejects bad arguments on the host before
+any HIP call."""
+
+import ctypes as C
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import scenegen
+from scenegen import Camera
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def rt():
+    import paper_2305_07450_amd as rt
+    return rt
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "rt.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[\w\s\*]+?\b(rt_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_header_declares_the_entry_points():
+    syms = declared_symbols()
+    for s in ("rt_scene_upload", "rt_scene_update", "rt_scene_destroy", "rt_records_bytes",
+              "rt_render", "rt_render_counts", "rt_render_backward", "rt_batch_create",
+              "rt_batch_launch", "rt_batch_destroy", "rt_status_string", "rt_last_error"):
+        assert s in syms
+
+
+def test_library_exports_every_declared_symbol(rt):
+    lib = C.CDLL(rt.LIB_PATH)
+    missing = [s for s in declared_symbols() if not hasattr(lib, s)]
+    assert not missing, missing
+
+
+def test_binding_wraps_every_declared_symbol(rt):
+    missing = [s for s in declared_symbols() if not hasattr(rt, s)]
+    assert not missing, missing
+
+
+def test_status_strings(rt):
+    assert rt.rt_status_string(0) == "RT_OK"
+    assert rt.rt_status_string(1) == "RT_ERR_INVALID_ARG"
+    assert rt.rt_status_string(4) == "RT_ERR_UNSUPPORTED"
+
+
+def test_records_bytes(rt):
+    assert rt.rt_records_bytes(1920, 1080, 4) == 1920 * 1080 * 5 * 5
+    assert rt.rt_records_bytes(0, 10, 1) == -1
+    assert rt.rt_records_bytes(10, 10, 9) == -1
+    assert rt.rt_records_bytes(10, 10, -1) == -1
+
+
+def _bad_scenes():
+    base = scenegen.tiny_scene(1, n_spheres=3, n_lights=2)
+    out = []
+
+    def mod(name, f):
+        s = base.copy()
+        f(s)
+        out.append((name, s))
+
+    mod("radius_zero", lambda s: s.sphere_geom.__setitem__((0, 3), 0.0))
+    mod("radius_negative", lambda s: s.sphere_geom.__setitem__((1, 3), -1.0))
+    mod("nan_centre", lambda s: s.sphere_geom.__setitem__((0, 0), np.nan))
+    mod("inf_albedo", lambda s: s.sphere_mat.__setitem__((2, 1), np.inf))
+    mod("zero_exponent", lambda s: s.sphere_shine.__setitem__(0, 0.0))
+    mod("plane_not_unit", lambda s: s.plane_geom.__setitem__((0, 1), 2.0))
+    mod("negative_light", lambda s: s.light.__setitem__((1, 3), -0.5))
+    mod("nan_light", lambda s: s.light.__setitem__((0, 2), np.nan))
+    mod("negative_tmin", lambda s: setattr(s, "t_min", -1.0))
+    mod("bad_spec_model", lambda s: setattr(s, "spec_model", 7))
+    mod("nan_ambient", lambda s: setattr(s, "ambient", float("nan")))
+    return out
+
+
+@pytest.mark.parametrize("name,scene", _bad_scenes(), ids=[n for n, _ in _bad_scenes()])
+def test_upload_rejects_bad_values_before_any_device_call(rt, name, scene):
+    with pytest.raises(rt.RtError) as e:
+        rt.rt_scene_upload(scene, stream=0)
+    assert e.value.status == rt.RT_ERR_INVALID_ARG, str(e.value)
+
+
+def test_upload_rejects_bad_counts(rt):
+    s = scenegen.tiny_scene(1, n_spheres=3, n_lights=1)
+    d = rt._Desc(s)
+    for field, val in (("n_spheres", -1), ("n_spheres", rt.RT_MAX_SPHERES + 1),
+                       ("n_planes", rt.RT_MAX_PLANES + 1), ("n_lights", rt.RT_MAX_LIGHTS + 1),
+                       ("mem", 5)):
+        c = rt.rt_scene_desc.from_buffer_copy(d.c)
+        setattr(c, field, val)
+        h = C.c_void_p()
+        st = rt._lib.rt_scene_upload(C.byref(c), None, C.byref(h))
+        assert st == rt.RT_ERR_INVALID_ARG and not h.value, (field, val)
+    c = rt.rt_scene_desc.from_buffer_copy(d.c)
+    c.sphere_geom = None
+    assert rt._lib.rt_scene_upload(C.byref(c), None, C.byref(C.c_void_p())) == 1
+    assert rt._lib.rt_scene_upload(None, None, C.byref(C.c_void_p())) == 1
+    assert rt._lib.rt_scene_upload(C.byref(d.c), None, None) == 1
+    assert "out is NULL" in rt.rt_last_error()
+
+
+FAKE_SCENE = 0x10   # never dereferenced: every case below fails validation first
+
+
+@pytest.mark.parametrize("cam,W,H,D", [
+    (Camera(fov_deg=0.0), 8, 8, 1), (Camera(fov_deg=180.0), 8, 8, 1),
+    (Camera(eye=(0.0, float("nan"), 0.0)), 8, 8, 1), (Camera(yaw_deg=float("inf")), 8, 8, 1),
+    (Camera(), 0, 8, 1), (Camera(), 8, -3, 1), (Camera(), 16385, 8, 1),
+    (Camera(), 8, 8, -1), (Camera(), 8, 8, 9)])
+def test_render_rejects_bad_camera_and_sizes(rt, cam, W, H, D):
+    c = rt.make_camera(cam)
+    st = rt._lib.rt_render(FAKE_SCENE, C.byref(c), W, H, D, 0x1000, None, None, None)
+    assert st == rt.RT_ERR_INVALID_ARG
+    st = rt._lib.rt_render_backward(FAKE_SCENE, C.byref(c), W, H, D, 0x1000, None,
+                                    C.byref(rt.rt_grads()), None)
+    assert st == rt.RT_ERR_INVALID_ARG
+
+
+def test_render_rejects_null_buffers_and_short_records(rt):
+    c = rt.make_camera(Camera())
+    assert rt._lib.rt_render(None, C.byref(c), 8, 8, 1, 0x1000, None, None, None) == 1
+    assert rt._lib.rt_render(FAKE_SCENE, C.byref(c), 8, 8, 1, None, None, None, None) == 1
+    assert rt._lib.rt_render(FAKE_SCENE, None, 8, 8, 1, 0x1000, None, None, None) == 1
+    rec = rt.rt_records(0x1000, 0x2000, rt.rt_records_bytes(8, 8, 1) - 1)
+    assert rt._lib.rt_render(FAKE_SCENE, C.byref(c), 8, 8, 1, 0x1000, None, C.byref(rec),
+                             None) == 1
+    assert "records hold" in rt.rt_last_error()
+    rec = rt.rt_records(None, 0x2000, 1 << 20)
+    assert rt._lib.rt_render(FAKE_SCENE, C.byref(c), 8, 8, 1, 0x1000, None, C.byref(rec),
+                             None) == 1
+    assert rt._lib.rt_render_backward(FAKE_SCENE, C.byref(c), 8, 8, 1, None, None,
+                                      C.byref(rt.rt_grads()), None) == 1
+    assert rt._lib.rt_render_backward(FAKE_SCENE, C.byref(c), 8, 8, 1, 0x1000, None, None,
+                                      None) == 1
+    assert rt._lib.rt_render_counts(FAKE_SCENE, C.byref(c), 8, 8, 1, None, None) == 1
+
+
+def test_destroy_null_is_a_no_op(rt):
+    assert rt._lib.rt_scene_destroy(None) == 0

@@ -1,0 +1,127 @@
+"""Forward parity of the HIP render kernel against the FP64 oracle (GPU)."""
+
+import zlib
+
+import numpy as np
+import pytest
+import torch
+
+import scenegen
+from scenegen import Camera, Scene, SPEC_BLINN, SPEC_PHONG
+
+from .gpu_common import compare, gpu_render, log
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rt():
+    assert torch.cuda.is_available(), "GPU test without a GPU"
+    import paper_2305_07450_amd as rt
+    return rt
+
+
+@pytest.mark.parametrize("seed", [None] + list(range(10)))
+def test_workload0_full_frame(rt, oracle_mod, seed):
+    """256x144, 8 spheres, 1 light, depth 2: every pixel."""
+    wl = scenegen.make_workload(0, seed)
+    log("case workload0", wl.scene.digest(), "seed", seed)
+    g = gpu_render(rt, wl.scene, wl.camera, wl.W, wl.H, wl.depth, records=True)
+    compare(oracle_mod, wl.scene, wl.camera, wl.W, wl.H, wl.depth, g, label=f"w0 seed={seed}")
+
+
+EDGE_CASES = [
+    # (name, W, H, depth, n_spheres, n_lights, plane, spec, camera)
+    ("ragged", 37, 23, 2, 6, 1, True, SPEC_BLINN, Camera()),
+    ("one_pixel", 1, 1, 3, 5, 1, True, SPEC_BLINN, Camera()),
+    ("column", 1, 97, 2, 5, 2, True, SPEC_BLINN, Camera()),
+    ("row", 131, 1, 2, 5, 2, True, SPEC_BLINN, Camera()),
+    ("portrait", 48, 80, 2, 8, 1, True, SPEC_PHONG, Camera(fov_deg=75.0)),
+    ("depth0", 64, 36, 0, 8, 2, True, SPEC_BLINN, Camera()),
+    ("depth_max", 64, 36, 8, 12, 2, True, SPEC_BLINN, Camera()),
+    ("lights_max", 48, 27, 2, 8, 8, True, SPEC_BLINN, Camera()),
+    ("no_lights", 48, 27, 2, 8, 0, True, SPEC_BLINN, Camera()),
+    ("no_planes", 64, 36, 3, 10, 1, False, SPEC_PHONG, Camera()),
+    ("no_spheres", 64, 36, 2, 0, 1, True, SPEC_BLINN, Camera()),
+    ("empty_scene", 16, 9, 2, 0, 1, False, SPEC_BLINN, Camera()),
+    ("rotated", 80, 45, 3, 10, 2, True, SPEC_BLINN,
+     Camera(eye=(0.5, 0.25, 1.0), yaw_deg=12.0, pitch_deg=-7.5, fov_deg=50.0)),
+    ("many_spheres", 72, 40, 2, 300, 2, True, SPEC_BLINN, Camera()),
+]
+
+
+@pytest.mark.parametrize("case", EDGE_CASES, ids=[c[0] for c in EDGE_CASES])
+def test_edge_cases(rt, oracle_mod, case):
+    name, W, H, D, N, L, plane, spec, cam = case
+    s = scenegen.tiny_scene(zlib.crc32(name.encode()) % 1000, n_spheres=N, n_lights=L, with_plane=plane,
+                            spec_model=spec)
+    if name == "no_planes":
+        s.background = (0.25, 0.5, 0.75)
+        s = Scene(**{k: getattr(s, k) for k in s.__dataclass_fields__})
+    log("case", name, W, H, D, N, L)
+    g = gpu_render(rt, s, cam, W, H, D, records=True)
+    compare(oracle_mod, s, cam, W, H, D, g, label=name)
+
+
+def test_records_do_not_change_image_and_runs_repeat(rt):
+    wl = scenegen.make_workload(0, 3)
+    a = gpu_render(rt, wl.scene, wl.camera, wl.W, wl.H, wl.depth, records=True)
+    b = gpu_render(rt, wl.scene, wl.camera, wl.W, wl.H, wl.depth, records=False)
+    c = gpu_render(rt, wl.scene, wl.camera, wl.W, wl.H, wl.depth, records=False)
+    assert np.array_equal(a["rgb"], b["rgb"]) and np.array_equal(b["rgb"], c["rgb"])
+    assert np.array_equal(a["ids"], b["ids"])
+
+
+def test_scene_update_in_place(rt, oracle_mod):
+    """rt_scene_update with host and with device arrays gives the image of the new scene."""
+    wl = scenegen.make_workload(0, 5)
+    s2 = scenegen.perturb_scene(wl.scene, np.random.default_rng(1), sigma=0.2)
+    h = rt.SceneHandle(wl.scene)
+    try:
+        rt.rt_scene_update(h.handle, s2)
+        rgb, ids, _ = rt.render(h.handle, wl.camera, wl.W, wl.H, wl.depth, ids=True)
+        dev = {k: torch.as_tensor(getattr(s2, k)).cuda() for k in (
+            "sphere_geom", "sphere_mat", "sphere_shine", "plane_geom", "plane_mat",
+            "plane_shine", "light")}
+        keep = rt.rt_scene_update(h.handle, s2, arrays=dev)
+        rgb2, ids2, _ = rt.render(h.handle, wl.camera, wl.W, wl.H, wl.depth, ids=True)
+        torch.cuda.synchronize()
+        del keep
+    finally:
+        h.close()
+    assert torch.equal(rgb, rgb2) and torch.equal(ids, ids2)
+    g = dict(rgb=rgb.cpu().numpy().reshape(-1, 3).astype(np.float64),
+             ids=ids.cpu().numpy().reshape(-1))
+    compare(oracle_mod, s2, wl.camera, wl.W, wl.H, wl.depth, g, label="updated")
+
+
+@pytest.mark.parametrize("config,row_step", [(1, 1), (2, 8), (4, 1)])
+def test_full_size_sampled_rows(rt, oracle_mod, config, row_step):
+    """Full-size workloads rendered whole on the GPU, in the launch the
+    benchmark times; the oracle checks every pixel of a row sample."""
+    wl = scenegen.make_workload(config)
+    log("case full-size", wl.name, "rows every", row_step)
+    g = gpu_render(rt, wl.scene, wl.camera, wl.W, wl.H, wl.depth)
+    rows = np.arange(0, wl.H, row_step)
+    rows = np.unique(np.concatenate([rows, [wl.H - 1]]))
+    pixels = (rows[:, None] * wl.W + np.arange(wl.W)[None, :]).reshape(-1)
+    compare(oracle_mod, wl.scene, wl.camera, wl.W, wl.H, wl.depth, g, pixels=pixels,
+            label=wl.name)
+
+
+@pytest.mark.parametrize("config", [0, 1, 4])
+def test_work_counters_match_oracle(rt, oracle_mod, config):
+    """The kernel's algorithmic counters equal the oracle's, up to the few
+    decisions taken differently at grazing pixels."""
+    wl = scenegen.make_workload(config)
+    h = rt.SceneHandle(wl.scene)
+    try:
+        got = rt.render_counts(h.handle, wl.camera, wl.W, wl.H, wl.depth)
+    finally:
+        h.close()
+    want = oracle_mod.render(wl.scene, wl.camera, wl.W, wl.H, wl.depth, records=False,
+                             margins=False).counts
+    log("counts", wl.name, got, want)
+    assert got["primary_rays"] == want["primary_rays"] == wl.W * wl.H
+    for k in want:
+        assert abs(got[k] - want[k]) <= 1e-3 * max(want[k], 1), (k, got[k], want[k])
