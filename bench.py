@@ -73,6 +73,95 @@ def cpu_baseline(wl, seconds: float):
                       f"{per_frame:.3f} s per frame, FP64 C oracle with OpenMP"}
 
 
+def time_gpu(fn, steps, warmup, stream):
+    """Mean GPU time per call of fn() (HIP events on `stream`), in ms."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def bench_fwd_bwd(rt, scenegen, stream, steps):
+    """Differentiable workload (1280x720, 128 spheres, 1 light, depth 3):
+    forward render with records + adjoint, and with re-traced decisions."""
+    import torch
+    prob = scenegen.make_diff_problem()
+    wl = prob.workload
+    W, H, D = wl.W, wl.H, wl.depth
+    h = rt.SceneHandle(wl.scene)
+    rgb = torch.empty((H, W, 3), device="cuda")
+    grad = torch.ones((H, W, 3), device="cuda")
+    N, L = wl.scene.n_spheres, wl.scene.n_lights
+    g = {k: torch.empty(sh, device="cuda") for k, sh in (
+        ("albedo", (N, 3)), ("refl", (N,)), ("center", (N, 3)), ("light_pos", (L, 3)),
+        ("light_int", (L,)))}
+    rec = rt.Records(W, H, D)
+    t_fwd = time_gpu(lambda: rt.rt_render(h.handle, wl.camera, W, H, D, rgb, None, rec, stream),
+                     steps, 5, stream)
+    t_bwd = time_gpu(lambda: rt.rt_render_backward(h.handle, wl.camera, W, H, D, grad, g, rec,
+                                                   stream), steps, 5, stream)
+    t_bwd_re = time_gpu(lambda: rt.rt_render_backward(h.handle, wl.camera, W, H, D, grad, g,
+                                                      None, stream), steps, 5, stream)
+    t_fwd_plain = time_gpu(lambda: rt.rt_render(h.handle, wl.camera, W, H, D, rgb, None, None,
+                                                stream), steps, 5, stream)
+    h.close()
+    P = W * H
+    return {"workload": wl.name,
+            "fwd_ms": round(t_fwd, 4), "bwd_ms": round(t_bwd, 4),
+            "fwd_bwd_mrays_per_s_checkpoint": round(P / ((t_fwd + t_bwd) * 1e-3) / 1e6, 2),
+            "bwd_recompute_ms": round(t_bwd_re, 4),
+            "fwd_bwd_mrays_per_s_recompute": round(P / ((t_fwd_plain + t_bwd_re) * 1e-3) / 1e6,
+                                                   2),
+            "fwd_only_mrays_per_s": round(P / (t_fwd_plain * 1e-3) / 1e6, 2)}
+
+
+def bench_batch(rt, scenegen, stream, steps):
+    """64 scenes of uneven size in one graph-captured persistent launch, against
+    64 rt_render calls back to back on one stream."""
+    import torch
+    wls = scenegen.make_batch()
+    handles = [rt.SceneHandle(w.scene) for w in wls]
+    outs = [torch.empty((w.H, w.W, 3), device="cuda") for w in wls]
+    t0 = time.perf_counter()
+    b = rt.rt_batch_create([h.handle for h in handles], [w.camera for w in wls],
+                           [w.W for w in wls], [w.H for w in wls], [w.depth for w in wls], outs,
+                           autotune=True, stream=stream)
+    create_s = time.perf_counter() - t0
+    t_graph = time_gpu(lambda: rt.rt_batch_launch(b, stream), steps, 3, stream)
+
+    def sequential():
+        for w, h, o in zip(wls, handles, outs):
+            rt.rt_render(h.handle, w.camera, w.W, w.H, w.depth, o, None, None, stream)
+    t_seq = time_gpu(sequential, steps, 3, stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        sequential()
+    torch.cuda.synchronize()
+    t_seq_wall = (time.perf_counter() - t1) * 1e3 / steps
+    shape = rt.rt_batch_shape(b)
+    rt.rt_batch_destroy(b)
+    for h in handles:
+        h.close()
+    P = sum(w.W * w.H for w in wls)
+    return {"workload": "batch_64scenes", "scenes": len(wls), "pixels": P,
+            "graph_ms": round(t_graph, 4), "sequential_ms_gpu": round(t_seq, 4),
+            "sequential_ms_wall": round(t_seq_wall, 4),
+            "batched_mrays_per_s": round(P / (t_graph * 1e-3) / 1e6, 2),
+            "sequential_mrays_per_s": round(P / (max(t_seq, t_seq_wall) * 1e-3) / 1e6, 2),
+            "speedup": round(max(t_seq, t_seq_wall) / t_graph, 3),
+            "shape": {"workgroups": shape[0], "tile_w": shape[1], "tile_h": shape[2]},
+            "create_s": round(create_s, 3)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -81,6 +170,11 @@ def main():
     ap.add_argument("--workload", type=int, default=1, choices=[0, 1, 2, 4])
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="first run one device-to-device copy of this many MiB (a kernel of "
+                         "known traffic, to calibrate HBM byte counters)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched and forward+backward measurements")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -92,6 +186,12 @@ def main():
     import paper_2305_07450_amd as rt
     import scenegen
 
+    if args.copy_mib:
+        a = torch.ones(args.copy_mib << 18, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     wl = scenegen.make_workload(args.workload)
     W, H, D = wl.W, wl.H, wl.depth
     dev = torch.device("cuda:0")
@@ -144,6 +244,9 @@ def main():
                      "flops_per_launch": flops},
     }
     h.close()
+    if not args.no_extras:
+        out["fwd_bwd"] = bench_fwd_bwd(rt, scenegen, stream, 20)
+        out["batch"] = bench_batch(rt, scenegen, stream, 10)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -148,6 +148,20 @@ int64_t rt_records_bytes(int32_t W, int32_t H, int32_t depth);
 rt_status rt_render(rt_scene scene, const rt_camera* cam, int32_t W, int32_t H, int32_t depth,
                     float* rgb_out, int32_t* id_out, const rt_records* rec, void* stream);
 
+/* Flags of rt_render_ex. */
+#define RT_RENDER_NO_PREFILTER 1u  /* run the exact ray-primitive test on every
+                                      pair: the cheap tests that skip pairs
+                                      (cones from the eye and the lights, the
+                                      mirror-ray bound) only skip pairs the
+                                      exact test rejects, so the image is the
+                                      same bits either way; this flag exists
+                                      to check that */
+
+/* rt_render with flags (0 = rt_render). */
+rt_status rt_render_ex(rt_scene scene, const rt_camera* cam, int32_t W, int32_t H, int32_t depth,
+                       float* rgb_out, int32_t* id_out, const rt_records* rec, uint32_t flags,
+                       void* stream);
+
 /* Work counters of the render of one image, as the method defines its work
  * (Sections 3.4.1 and 3.6: every segment tests every primitive; a shadow ray
  * is traced only when n.L > 0 and tests primitives in ascending id order up

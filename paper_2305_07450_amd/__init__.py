@@ -26,6 +26,7 @@ RT_MAX_DEPTH = 8
 RT_MAX_LIGHTS = 8
 RT_MAX_SPHERES = 4096
 RT_MAX_PLANES = 16
+RT_RENDER_NO_PREFILTER = 1
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(
@@ -73,6 +74,8 @@ _sig = {
     "rt_records_bytes": (C.c_int64, [_i32, _i32, _i32]),
     "rt_render": (C.c_int, [_vp, C.POINTER(rt_camera), _i32, _i32, _i32, _vp, _vp,
                             C.POINTER(rt_records), _vp]),
+    "rt_render_ex": (C.c_int, [_vp, C.POINTER(rt_camera), _i32, _i32, _i32, _vp, _vp,
+                               C.POINTER(rt_records), C.c_uint32, _vp]),
     "rt_render_counts": (C.c_int, [_vp, C.POINTER(rt_camera), _i32, _i32, _i32, _vp, _vp]),
     "rt_render_backward": (C.c_int, [_vp, C.POINTER(rt_camera), _i32, _i32, _i32, _vp,
                                      C.POINTER(rt_records), C.POINTER(rt_grads), _vp]),
@@ -200,6 +203,15 @@ def rt_render(handle: int, camera, W: int, H: int, depth: int, rgb_out: torch.Te
     cam = make_camera(camera)
     _check(_lib.rt_render(handle, C.byref(cam), W, H, depth, _ptr(rgb_out), _ptr(id_out),
                           C.byref(rec.c) if rec is not None else None, _stream(stream)))
+
+
+def rt_render_ex(handle: int, camera, W: int, H: int, depth: int, rgb_out: torch.Tensor,
+                 id_out: Optional[torch.Tensor] = None, rec: Optional["Records"] = None,
+                 flags: int = 0, stream=None):
+    cam = make_camera(camera)
+    _check(_lib.rt_render_ex(handle, C.byref(cam), W, H, depth, _ptr(rgb_out), _ptr(id_out),
+                             C.byref(rec.c) if rec is not None else None, int(flags),
+                             _stream(stream)))
 
 
 COUNT_NAMES = ("sphere_tests", "plane_tests", "primary_rays", "reflection_rays", "shadow_rays")

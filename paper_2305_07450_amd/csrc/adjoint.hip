@@ -43,10 +43,11 @@ __device__ __forceinline__ void light_terms_fixed(const SceneDev& s, const Surfa
     if (!((lit >> l) & 1u)) continue;
     float4 q = ld4(s.light, l);
     float lx = q.x - f.px, ly = q.y - f.py, lz = q.z - f.pz;
-    float dist = __builtin_sqrtf(dot3(lx, ly, lz, lx, ly, lz));
-    lx = lx / dist;
-    ly = ly / dist;
-    lz = lz / dist;
+    float d2 = dot3(lx, ly, lz, lx, ly, lz);
+    float inv = frsq(d2);
+    lx *= inv;
+    ly *= inv;
+    lz *= inv;
     float nl = dot3(f.nx, f.ny, f.nz, lx, ly, lz);
     A = fmaf(q.w, nl, A);
     float x = spec_base(s.spec_model, f.nx, f.ny, f.nz, lx, ly, lz, -r.dx, -r.dy, -r.dz, nl);
@@ -207,8 +208,10 @@ __global__ __launch_bounds__(256) void adjoint_kernel(SceneDev s, CameraDev c, i
             if (!((rr.lits[k] >> l) & 1u)) continue;
             float4 q = ld4(s.light, l);
             V3 lv = {q.x - f.px, q.y - f.py, q.z - f.pz};
-            float dist = __builtin_sqrtf(dotv(lv, lv));
-            V3 ld = {lv.x / dist, lv.y / dist, lv.z / dist};
+            float d2 = dotv(lv, lv);
+            float inv = frsq(d2);
+            float dist = d2 * inv;
+            V3 ld = {lv.x * inv, lv.y * inv, lv.z * inv};
             float nl = dotv(n, ld);
             V3 ldbar = {Abar * q.w * n.x, Abar * q.w * n.y, Abar * q.w * n.z};
             nbar.x += Abar * q.w * ld.x;
@@ -338,13 +341,32 @@ __global__ __launch_bounds__(256) void adjoint_kernel(SceneDev s, CameraDev c, i
   }
 }
 
-// Sum the workgroup partials in block order and scatter to the caller's arrays.
-__global__ void reduce_kernel(const float* __restrict__ partials, int stride, int blocks, int N,
-                              int L, rt_grads g) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= 7 * N + 4 * L) return;
+// Sum the workgroup partials and scatter to the caller's arrays.  A workgroup
+// owns 64 consecutive entries; its four waves add every fourth partial (rows
+// b = w, w + 4, ...; one coalesced 256-byte row read per wave per step), then
+// wave 0 adds the four wave sums in wave order.  The order is fixed, so the
+// result does not depend on timing.
+constexpr int kReduceCols = 64;
+constexpr int kReduceWaves = 4;
+
+__global__ __launch_bounds__(256) void reduce_kernel(const float* __restrict__ partials,
+                                                      int stride, int blocks, int N, int L,
+                                                      rt_grads g) {
+  __shared__ float part[kReduceWaves][kReduceCols];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int total = 7 * N + 4 * L;
+  const int j = blockIdx.x * kReduceCols + lane;
   float sum = 0.0f;
-  for (int b = 0; b < blocks; ++b) sum += partials[(int64_t)b * stride + j];
+  if (j < total) {
+#pragma unroll 8
+    for (int b = wave; b < blocks; b += kReduceWaves) sum += partials[(int64_t)b * stride + j];
+  }
+  part[wave][lane] = sum;
+  __syncthreads();
+  if (wave != 0 || j >= total) return;
+  sum = part[0][lane];
+  for (int w = 1; w < kReduceWaves; ++w) sum += part[w][lane];
   if (j < 7 * N) {
     const int i = j / 7, c = j % 7;
     if (c < 3) {
@@ -392,7 +414,8 @@ hipError_t launch_backward(const rt_scene_s& sc, const CameraDev& c, int depth,
   if (e != hipSuccess) return e;
   const int total = 7 * N + 4 * L;
   if (total == 0) return hipSuccess;
-  hipLaunchKernelGGL(reduce_kernel, dim3((total + 255) / 256), dim3(256), 0, stream,
+  hipLaunchKernelGGL(reduce_kernel, dim3((total + kReduceCols - 1) / kReduceCols),
+                     dim3(64 * kReduceWaves), 0, stream,
                      (const float*)sc.partials, sc.grad_stride, blocks, N, L, g);
   return hipGetLastError();
 }

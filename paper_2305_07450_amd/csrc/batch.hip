@@ -1,30 +1,393 @@
-// batch.hip - batched persistent launch (not built yet: every entry point
-// reports RT_ERR_UNSUPPORTED).
+// batch.hip - many scenes of uneven size in one persistent launch.
+//
+// The host flattens every image into pixel tiles and orders the tile queue by
+// estimated cost, largest first (LPT: a tile's cost is taken as pixels x
+// segments x primitives x (1 + lights), the brute-force work of Sections
+// 3.4-3.7).  A persistent grid of workgroups pulls tiles from the queue with
+// one atomic counter per launch; each workgroup reads the job descriptor of
+// its tile through scalar loads and renders it with exactly the per-pixel code
+// of rt_render (trace.hpp), so every image is bit-identical to a single
+// rt_render of the same scene.  The counter is reset by a one-lane kernel in
+// the same stream (no memset node), and both kernels are captured once into a
+// HIP graph that rt_batch_launch replays.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
 #include "rt_internal.hpp"
+
+namespace rtk {
+
+struct BatchJob {
+  SceneDev s;
+  CameraDev c;
+  int depth;
+  int tiles_x;
+  float* rgb;
+};
+static_assert(sizeof(BatchJob) % 4 == 0, "descriptor is copied in 32-bit words");
+
+// One queue entry: job index and tile index within the job.
+struct TileRef {
+  int job;
+  int tile;
+};
+
+struct Shape {
+  int waves;   // wave64s per workgroup
+  int wave_w;  // pixel columns per wave (wave_w * wave_h = 64)
+  int grid;    // persistent workgroups
+};
+
+__global__ void reset_counter_kernel(unsigned int* counter) { *counter = 0u; }
+
+// Eye cones of every job's spheres (grid.y = job), into the batch's own table.
+__global__ void batch_cone_kernel(const BatchJob* __restrict__ jobs, float4* const* cones) {
+  const BatchJob& j = jobs[blockIdx.y];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < j.s.n_spheres) {
+    float4 g = j.s.geom[i];
+    cones[blockIdx.y][i] = sphere_cone(j.c.ex, j.c.ey, j.c.ez, g.x, g.y, g.z, j.s.rad[i].x);
+  } else if (i < j.s.n4 + kGroup) {
+    cones[blockIdx.y][i] = make_float4(0.0f, 0.0f, 0.0f, kPadConeW);
+  }
+}
+
+__global__ __launch_bounds__(256) void batch_kernel(const BatchJob* __restrict__ jobs,
+                                                     const TileRef* __restrict__ queue,
+                                                     int n_tiles, unsigned int* counter,
+                                                     int wave_w) {
+  __shared__ int s_tile;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int waves = blockDim.x >> 6;
+  const int wave_h = 64 / wave_w;
+  const int tile_w = wave_w, tile_h = wave_h * waves;
+  for (;;) {
+    if (threadIdx.x == 0) s_tile = (int)atomicAdd(counter, 1u);
+    __syncthreads();
+    const int t = s_tile;
+    __syncthreads();   // every lane has read s_tile before it is written again
+    if (t >= n_tiles) break;   // uniform: the whole workgroup leaves together
+    const TileRef ref = queue[t];
+    const BatchJob* jp = jobs + __builtin_amdgcn_readfirstlane(ref.job);
+    // copy the descriptor word by word through the constant address space
+    // (uniform address -> scalar loads)
+    BatchJob job;
+    {
+      const RT_CONSTANT uint32_t* src = (const RT_CONSTANT uint32_t*)jp;
+      uint32_t* dst = (uint32_t*)&job;
+#pragma unroll
+      for (int i = 0; i < (int)(sizeof(BatchJob) / 4); ++i) dst[i] = src[i];
+    }
+    const int tile = __builtin_amdgcn_readfirstlane(ref.tile);
+    const int tx = tile % job.tiles_x, ty = tile / job.tiles_x;
+    const int x = tx * tile_w + (lane % wave_w);
+    const int y = ty * tile_h + wave * wave_h + (lane / wave_w);
+    if (x < job.c.W && y < job.c.H) {
+      float cr, cg, cb;
+      int prim;
+      NoRecords sink;
+      trace_path(job.s, primary_ray(job.c, x, y), job.depth, cr, cg, cb, prim, sink);
+      const int64_t pix = (int64_t)y * job.c.W + x;
+      job.rgb[3 * pix + 0] = cr;
+      job.rgb[3 * pix + 1] = cg;
+      job.rgb[3 * pix + 2] = cb;
+    }
+  }
+}
+
+}  // namespace rtk
 
 using namespace rtk;
 
+struct rt_batch_s {
+  int device = 0;
+  int n = 0;
+  int n_tiles = 0;
+  Shape shape{};
+  BatchJob* jobs = nullptr;     // device
+  TileRef* queue = nullptr;     // device
+  float4* cones = nullptr;      // device: eye cones of every job's spheres
+  float4** cone_ptr = nullptr;  // device: start of each job's cones
+  int max_spheres = 0;
+  unsigned int* counter = nullptr;
+  std::vector<BatchJob> host_jobs;
+  std::vector<double> job_cost;  // per tile
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+std::mutex g_tune_mu;
+std::map<std::string, Shape> g_tune_cache;
+
+rt_status err(rt_status st, const std::string& m) {
+  set_error(m);
+  return st;
+}
+
+// Build the LPT-ordered queue for a wave shape.
+std::vector<TileRef> build_queue(rt_batch_s* b, int wave_w, int waves) {
+  const int tile_w = wave_w, tile_h = (64 / wave_w) * waves;
+  std::vector<int> order(b->n);
+  for (int i = 0; i < b->n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int c) { return b->job_cost[a] > b->job_cost[c]; });
+  std::vector<TileRef> q;
+  for (int j : order) {
+    BatchJob& job = b->host_jobs[j];
+    job.tiles_x = (job.c.W + tile_w - 1) / tile_w;
+    const int tiles_y = (job.c.H + tile_h - 1) / tile_h;
+    for (int t = 0; t < job.tiles_x * tiles_y; ++t) q.push_back(TileRef{j, t});
+  }
+  return q;
+}
+
+hipError_t upload_shape(rt_batch_s* b, const Shape& sh, hipStream_t stream) {
+  std::vector<TileRef> q = build_queue(b, sh.wave_w, sh.waves);
+  hipError_t e = hipMemcpyAsync(b->jobs, b->host_jobs.data(), sizeof(BatchJob) * b->n,
+                                hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->queue, q.data(), sizeof(TileRef) * q.size(), hipMemcpyHostToDevice,
+                       stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  b->n_tiles = (int)q.size();
+  b->shape = sh;
+  return e;
+}
+
+hipError_t launch_batch(rt_batch_s* b, hipStream_t stream) {
+  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, stream, b->counter);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (b->max_spheres > 0) {
+    hipLaunchKernelGGL(batch_cone_kernel, dim3((b->max_spheres + 255) / 256, b->n), dim3(256), 0,
+                       stream, (const BatchJob*)b->jobs, (float4* const*)b->cone_ptr);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(batch_kernel, dim3(b->shape.grid), dim3(64 * b->shape.waves), 0, stream,
+                     b->jobs, b->queue, b->n_tiles, b->counter, b->shape.wave_w);
+  return hipGetLastError();
+}
+
+std::string signature(const rt_batch_s* b) {
+  std::string s = std::to_string(b->n);
+  for (const BatchJob& j : b->host_jobs)
+    s += ":" + std::to_string(j.c.W) + "x" + std::to_string(j.c.H) + "d" +
+         std::to_string(j.depth) + "n" + std::to_string(j.s.n_spheres) + "l" +
+         std::to_string(j.s.n_lights);
+  return s;
+}
+
+// Time each candidate shape with events (median of 3 direct launches).
+rt_status autotune(rt_batch_s* b, int cus, hipStream_t stream, Shape* best) {
+  const int wave_ws[] = {8, 16, 64};
+  const int wavess[] = {1, 2, 4};
+  const int grid_mult[] = {2, 4, 8};
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return err(RT_ERR_DEVICE, "autotune: event creation failed");
+  float best_ms = 1e30f;
+  rt_status st = RT_OK;
+  for (int ww : wave_ws)
+    for (int wv : wavess)
+      for (int gm : grid_mult) {
+        Shape sh{wv, ww, cus * gm * (4 / wv)};
+        hipError_t e = upload_shape(b, sh, stream);
+        float times[3];
+        for (int r = 0; r < 4 && e == hipSuccess; ++r) {
+          e = hipEventRecord(e0, stream);
+          if (e == hipSuccess) e = launch_batch(b, stream);
+          if (e == hipSuccess) e = hipEventRecord(e1, stream);
+          if (e == hipSuccess) e = hipEventSynchronize(e1);
+          if (e == hipSuccess && r > 0) e = hipEventElapsedTime(&times[r - 1], e0, e1);
+        }
+        if (e != hipSuccess) {
+          st = hip_fail(e, "autotune launch");
+          goto done;
+        }
+        std::sort(times, times + 3);
+        if (times[1] < best_ms) {
+          best_ms = times[1];
+          *best = sh;
+        }
+      }
+done:
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return st;
+}
+
+void free_batch(rt_batch_s* b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->jobs) (void)hipFree(b->jobs);
+  if (b->queue) (void)hipFree(b->queue);
+  if (b->counter) (void)hipFree(b->counter);
+  if (b->cones) (void)hipFree(b->cones);
+  if (b->cone_ptr) (void)hipFree(b->cone_ptr);
+  delete b;
+}
+
+}  // namespace
+
 extern "C" {
 
-rt_status rt_batch_create(int32_t, const rt_scene*, const rt_camera*, const int32_t*,
-                          const int32_t*, const int32_t*, float* const*, int32_t, void*,
+rt_status rt_batch_create(int32_t n, const rt_scene* scenes, const rt_camera* cams,
+                          const int32_t* W, const int32_t* H, const int32_t* depth,
+                          float* const* rgb_out, int32_t autotune_flag, void* stream_v,
                           rt_batch* out) {
-  if (out) *out = nullptr;
-  set_error("rt_batch_create is not available in this build");
-  return RT_ERR_UNSUPPORTED;
+  if (!out) return err(RT_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (n <= 0 || n > RT_MAX_BATCH)
+    return err(RT_ERR_INVALID_ARG, "batch size " + std::to_string(n) + " outside [1, " +
+                                       std::to_string(RT_MAX_BATCH) + "]");
+  if (!scenes || !cams || !W || !H || !depth || !rgb_out)
+    return err(RT_ERR_INVALID_ARG, "a batch array is NULL");
+  for (int i = 0; i < n; ++i) {
+    if (!scenes[i]) return err(RT_ERR_INVALID_ARG, "scene " + std::to_string(i) + " is NULL");
+    if (!rgb_out[i]) return err(RT_ERR_INVALID_ARG, "rgb_out " + std::to_string(i) + " is NULL");
+    const rt_camera& c = cams[i];
+    float v[6] = {c.eye[0], c.eye[1], c.eye[2], c.yaw_deg, c.pitch_deg, c.fov_deg};
+    for (float f : v)
+      if (!isfinite(f)) return err(RT_ERR_INVALID_ARG, "camera " + std::to_string(i) + " is not finite");
+    if (!(c.fov_deg > 0.0f && c.fov_deg < 180.0f))
+      return err(RT_ERR_INVALID_ARG, "camera " + std::to_string(i) + " fov outside (0, 180)");
+    if (W[i] <= 0 || H[i] <= 0 || W[i] > RT_MAX_DIM || H[i] > RT_MAX_DIM)
+      return err(RT_ERR_INVALID_ARG, "image " + std::to_string(i) + " size out of range");
+    if (depth[i] < 0 || depth[i] > RT_MAX_DEPTH)
+      return err(RT_ERR_INVALID_ARG, "depth " + std::to_string(i) + " outside [0, 8]");
+    if (scenes[i]->device != scenes[0]->device)
+      return err(RT_ERR_INVALID_ARG, "scenes live on different devices");
+  }
+  hipStream_t stream = (hipStream_t)stream_v;
+  rt_batch_s* b = new (std::nothrow) rt_batch_s();
+  if (!b) return err(RT_ERR_OUT_OF_MEMORY, "host allocation failed");
+  b->n = n;
+  b->device = scenes[0]->device;
+  size_t max_tiles = 0;
+  for (int i = 0; i < n; ++i) {
+    BatchJob j;
+    j.s = scenes[i]->view();
+    j.c = camera_dev(cams[i], W[i], H[i]);
+    j.depth = depth[i];
+    j.tiles_x = 0;
+    j.rgb = rgb_out[i];
+    b->host_jobs.push_back(j);
+    const rt_scene_s* sc = scenes[i];
+    b->job_cost.push_back(64.0 * (depth[i] + 1) * (sc->n_spheres + sc->n_planes + 1) *
+                          (1 + sc->n_lights));
+    // queue capacity: the most tiles any candidate shape makes (one-wave tiles)
+    size_t most = 0;
+    for (int ww : {8, 16, 64}) {
+      const int wh = 64 / ww;
+      most = std::max(most, (size_t)((W[i] + ww - 1) / ww) * (size_t)((H[i] + wh - 1) / wh));
+    }
+    max_tiles += most;
+  }
+  size_t total_spheres = 0;
+  for (int i = 0; i < n; ++i) {
+    total_spheres += pad_spheres(scenes[i]->n_spheres) + kGroup;
+    b->max_spheres = std::max(b->max_spheres, pad_spheres(scenes[i]->n_spheres) + kGroup);
+  }
+  int dev = 0, cus = 256;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipMalloc(&b->cones, sizeof(float4) * std::max<size_t>(total_spheres, 1));
+  if (e == hipSuccess) e = hipMalloc(&b->cone_ptr, sizeof(float4*) * n);
+  if (e == hipSuccess) {
+    std::vector<float4*> ptrs(n);
+    size_t off = 0;
+    for (int i = 0; i < n; ++i) {
+      ptrs[i] = b->cones + off;
+      b->host_jobs[i].s.eye_cone = ptrs[i];
+      off += pad_spheres(scenes[i]->n_spheres) + kGroup;
+    }
+    e = hipMemcpy(b->cone_ptr, ptrs.data(), sizeof(float4*) * n, hipMemcpyHostToDevice);
+  }
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipMalloc(&b->jobs, sizeof(BatchJob) * n);
+  if (e == hipSuccess) e = hipMalloc(&b->queue, sizeof(TileRef) * max_tiles);
+  if (e == hipSuccess) e = hipMalloc(&b->counter, sizeof(unsigned int));
+  if (e != hipSuccess) {
+    rt_status st = hip_fail(e, "batch allocation");
+    free_batch(b);
+    return st;
+  }
+  Shape sh{4, 8, cus * 4};
+  rt_status st = RT_OK;
+  if (autotune_flag) {
+    const std::string key = signature(b);
+    bool hit = false;
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      auto it = g_tune_cache.find(key);
+      if (it != g_tune_cache.end()) {
+        sh = it->second;
+        hit = true;
+      }
+    }
+    if (!hit) {
+      st = autotune(b, cus, stream, &sh);
+      if (st != RT_OK) {
+        free_batch(b);
+        return st;
+      }
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      g_tune_cache[key] = sh;
+    }
+  }
+  e = upload_shape(b, sh, stream);
+  // capture reset + persistent kernel into a graph on a private stream
+  hipStream_t cap = nullptr;
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    hipError_t le = launch_batch(b, cap);
+    e = hipStreamEndCapture(cap, &b->graph);
+    if (le != hipSuccess) e = le;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+  if (cap) (void)hipStreamDestroy(cap);
+  if (e != hipSuccess) {
+    st = hip_fail(e, "batch graph capture");
+    free_batch(b);
+    return st;
+  }
+  *out = b;
+  return RT_OK;
 }
-rt_status rt_batch_launch(rt_batch, void*) {
-  set_error("rt_batch_launch is not available in this build");
-  return RT_ERR_UNSUPPORTED;
+
+rt_status rt_batch_launch(rt_batch b, void* stream) {
+  if (!b) return err(RT_ERR_INVALID_ARG, "batch is NULL");
+  return hip_fail(hipGraphLaunch(b->exec, (hipStream_t)stream), "batch graph launch");
 }
-rt_status rt_batch_launch_direct(rt_batch, void*) {
-  set_error("rt_batch_launch_direct is not available in this build");
-  return RT_ERR_UNSUPPORTED;
+
+rt_status rt_batch_launch_direct(rt_batch b, void* stream) {
+  if (!b) return err(RT_ERR_INVALID_ARG, "batch is NULL");
+  return hip_fail(launch_batch(b, (hipStream_t)stream), "batch launch");
 }
-rt_status rt_batch_shape(rt_batch, int32_t*, int32_t*, int32_t*) {
-  set_error("rt_batch_shape is not available in this build");
-  return RT_ERR_UNSUPPORTED;
+
+rt_status rt_batch_shape(rt_batch b, int32_t* workgroups, int32_t* tile_w, int32_t* tile_h) {
+  if (!b) return err(RT_ERR_INVALID_ARG, "batch is NULL");
+  if (workgroups) *workgroups = b->shape.grid;
+  if (tile_w) *tile_w = b->shape.wave_w;
+  if (tile_h) *tile_h = (64 / b->shape.wave_w) * b->shape.waves;
+  return RT_OK;
 }
-rt_status rt_batch_destroy(rt_batch) { return RT_OK; }
+
+rt_status rt_batch_destroy(rt_batch b) {
+  free_batch(b);
+  return RT_OK;
+}
 
 }  // extern "C"

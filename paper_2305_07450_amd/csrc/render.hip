@@ -27,7 +27,7 @@ struct RecordSink {
   __device__ __forceinline__ void lit(int k, uint32_t m) { lit_plane[k * plane + pix] = (uint8_t)m; }
 };
 
-template <bool kRecords>
+template <bool kRecords, bool kPrefilter>
 __global__ __launch_bounds__(256) void render_kernel(SceneDev s, CameraDev c, int depth,
                                                       float* __restrict__ rgb,
                                                       int32_t* __restrict__ id_out,
@@ -44,14 +44,14 @@ __global__ __launch_bounds__(256) void render_kernel(SceneDev s, CameraDev c, in
   int prim;
   if (kRecords) {
     RecordSink sink{rec_ids, rec_lit, (int64_t)c.W * c.H, pix};
-    int traced = trace_path(s, r, depth, cr, cg, cb, prim, sink);
+    int traced = trace_path<RecordSink, NoCount, kPrefilter>(s, r, depth, cr, cg, cb, prim, sink);
     for (int k = traced; k <= depth; ++k) {
       rec_ids[k * sink.plane + pix] = kNotTraced;
       rec_lit[k * sink.plane + pix] = 0;
     }
   } else {
     NoRecords sink;
-    trace_path(s, r, depth, cr, cg, cb, prim, sink);
+    trace_path<NoRecords, NoCount, kPrefilter>(s, r, depth, cr, cg, cb, prim, sink);
   }
   rgb[3 * pix + 0] = cr;
   rgb[3 * pix + 1] = cg;
@@ -90,22 +90,28 @@ hipError_t launch_counts(const SceneDev& s, const CameraDev& c, int depth,
 }
 
 hipError_t launch_render(const SceneDev& s, const CameraDev& c, int depth, float* rgb,
-                         int32_t* ids, int32_t* rec_ids, uint8_t* rec_lit, hipStream_t stream) {
+                         int32_t* ids, int32_t* rec_ids, uint8_t* rec_lit, bool prefilter,
+                         hipStream_t stream) {
   dim3 grid((c.W + kBlock - 1) / kBlock, (c.H + kBlock - 1) / kBlock);
-  if (rec_ids)
-    hipLaunchKernelGGL(render_kernel<true>, grid, dim3(256), 0, stream, s, c, depth, rgb, ids,
-                       rec_ids, rec_lit);
-  else
-    hipLaunchKernelGGL(render_kernel<false>, grid, dim3(256), 0, stream, s, c, depth, rgb, ids,
-                       rec_ids, rec_lit);
+  auto kern = rec_ids ? (prefilter ? render_kernel<true, true> : render_kernel<true, false>)
+                      : (prefilter ? render_kernel<false, true> : render_kernel<false, false>);
+  hipLaunchKernelGGL(kern, grid, dim3(256), 0, stream, s, c, depth, rgb, ids, rec_ids, rec_lit);
   return hipGetLastError();
 }
 
 // Pack the desc-layout arrays into the kernels' layout: r^2 beside the centre,
 // (r, 1/r), sphere and plane materials in one id-indexed table.
 __global__ void pack_kernel(RawScene raw, int N, int P, int L, float4* geom, float2* rad,
-                            float4* mat, float* shine, float4* pgeom, float4* light) {
+                            float4* mat, float* shine, float4* pgeom, float4* light,
+                            float4* light_cone) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n4 = pad_spheres(N);
+  if (i >= N && i < n4 + kGroup) {
+    // padding spheres: never hit, never inside a cone
+    geom[i] = make_float4(0.0f, 0.0f, 0.0f, kPadR2);
+    for (int l = 0; l < L; ++l)
+      if (i < n4 || l == L - 1) light_cone[(int64_t)l * n4 + i] = make_float4(0.f, 0.f, 0.f, kPadConeW);
+  }
   if (i < N) {
     const float* g = raw.sphere_geom + 4 * i;
     float r = g[3];
@@ -114,6 +120,10 @@ __global__ void pack_kernel(RawScene raw, int N, int P, int L, float4* geom, flo
     const float* m = raw.sphere_mat + 4 * i;
     mat[i] = make_float4(m[0], m[1], m[2], m[3]);
     shine[i] = raw.sphere_shine[i];
+    for (int l = 0; l < L; ++l) {
+      const float* q = raw.light + 4 * l;
+      light_cone[(int64_t)l * n4 + i] = sphere_cone(q[0], q[1], q[2], g[0], g[1], g[2], r);
+    }
   }
   if (i < P) {
     const float* g = raw.plane_geom + 4 * i;
@@ -128,14 +138,113 @@ __global__ void pack_kernel(RawScene raw, int N, int P, int L, float4* geom, flo
   }
 }
 
+// Scene centre C (middle of the sphere centres' bounding box), largest radius
+// and largest |c - C|, for the mirror-ray prefilter.  One workgroup.
+__global__ __launch_bounds__(256) void bounds_kernel(const float4* __restrict__ geom,
+                                                     const float2* __restrict__ rad, int N,
+                                                     float4* __restrict__ consts) {
+  __shared__ float red[7][256];
+  const int t = threadIdx.x;
+  float lo[3] = {3.0e38f, 3.0e38f, 3.0e38f}, hi[3] = {-3.0e38f, -3.0e38f, -3.0e38f}, rmax = 0.f;
+  for (int i = t; i < N; i += 256) {
+    float4 g = geom[i];
+    lo[0] = fminf(lo[0], g.x); lo[1] = fminf(lo[1], g.y); lo[2] = fminf(lo[2], g.z);
+    hi[0] = fmaxf(hi[0], g.x); hi[1] = fmaxf(hi[1], g.y); hi[2] = fmaxf(hi[2], g.z);
+    rmax = fmaxf(rmax, rad[i].x);
+  }
+  for (int k = 0; k < 3; ++k) {
+    red[k][t] = lo[k];
+    red[3 + k][t] = hi[k];
+  }
+  red[6][t] = rmax;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) {
+      for (int k = 0; k < 3; ++k) {
+        red[k][t] = fminf(red[k][t], red[k][t + w]);
+        red[3 + k][t] = fmaxf(red[3 + k][t], red[3 + k][t + w]);
+      }
+      red[6][t] = fmaxf(red[6][t], red[6][t + w]);
+    }
+    __syncthreads();
+  }
+  float C[3];
+  for (int k = 0; k < 3; ++k) C[k] = N > 0 ? 0.5f * (red[k][0] + red[3 + k][0]) : 0.0f;
+  const float rm = red[6][0];
+  __syncthreads();
+  float cm = 0.0f;
+  for (int i = t; i < N; i += 256) {
+    float4 g = geom[i];
+    double dx = (double)g.x - C[0], dy = (double)g.y - C[1], dz = (double)g.z - C[2];
+    cm = fmaxf(cm, (float)sqrt(dx * dx + dy * dy + dz * dz) * 1.0001f);
+  }
+  red[0][t] = cm;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) red[0][t] = fmaxf(red[0][t], red[0][t + w]);
+    __syncthreads();
+  }
+  if (t == 0) {
+    consts[0] = make_float4(C[0], C[1], C[2], rm);
+    consts[1] = make_float4(red[0][0], 0.0f, 0.0f, 0.0f);
+  }
+}
+
+// Mirror-ray prefilter table: (c' = c - C, K = |c'|^2 - r^2 - G |c'|^2 - 12 u r^2),
+// built in double from the rounded c'; padding entries can never pass.
+__global__ void refl_kernel(const float4* __restrict__ geom, const float2* __restrict__ rad,
+                            int N, const float4* __restrict__ consts, float4* __restrict__ refl) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const float4 k0 = consts[0];
+  if (i < N) {
+    float4 g = geom[i];
+    float cx = (float)((double)g.x - k0.x), cy = (float)((double)g.y - k0.y),
+          cz = (float)((double)g.z - k0.z);
+    double r = rad[i].x;
+    double cc = (double)cx * cx + (double)cy * cy + (double)cz * cz;
+    double K = cc - r * r - (double)kReflGamma * cc - 12.0 * 5.9604644775390625e-08 * r * r;
+    refl[i] = make_float4(cx, cy, cz, (float)K);
+  } else if (i < pad_spheres(N) + kGroup) {
+    refl[i] = make_float4(0.0f, 0.0f, 0.0f, 1.0e30f);
+  }
+}
+
 hipError_t launch_pack(const rt_scene_s& sc, const RawScene& raw, hipStream_t stream) {
-  int n = sc.n_spheres;
+  int n = pad_spheres(sc.n_spheres) + kGroup;
   if (sc.n_planes > n) n = sc.n_planes;
   if (sc.n_lights > n) n = sc.n_lights;
-  if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(pack_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, raw,
                      sc.n_spheres, sc.n_planes, sc.n_lights, sc.geom, sc.rad, sc.mat, sc.shine,
-                     sc.pgeom, sc.light);
+                     sc.pgeom, sc.light, sc.light_cone);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(bounds_kernel, dim3(1), dim3(256), 0, stream, (const float4*)sc.geom,
+                     (const float2*)sc.rad, sc.n_spheres, sc.consts);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int nr = pad_spheres(sc.n_spheres) + kGroup;
+  hipLaunchKernelGGL(refl_kernel, dim3((nr + 255) / 256), dim3(256), 0, stream,
+                     (const float4*)sc.geom, (const float2*)sc.rad, sc.n_spheres,
+                     (const float4*)sc.consts, sc.refl);
+  return hipGetLastError();
+}
+
+__global__ void eye_cone_kernel(const float4* __restrict__ geom, const float2* __restrict__ rad,
+                                int N, float ex, float ey, float ez, float4* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) {
+    float4 g = geom[i];
+    out[i] = sphere_cone(ex, ey, ez, g.x, g.y, g.z, rad[i].x);
+  } else if (i < pad_spheres(N) + kGroup) {
+    out[i] = make_float4(0.0f, 0.0f, 0.0f, kPadConeW);
+  }
+}
+
+hipError_t launch_eye_cones(const rt_scene_s& sc, const CameraDev& c, hipStream_t stream) {
+  hipLaunchKernelGGL(eye_cone_kernel, dim3((pad_spheres(sc.n_spheres) + kGroup + 255) / 256), dim3(256), 0,
+                     stream,
+                     (const float4*)sc.geom, (const float2*)sc.rad, sc.n_spheres, c.ex, c.ey,
+                     c.ez, sc.eye_cone);
   return hipGetLastError();
 }
 

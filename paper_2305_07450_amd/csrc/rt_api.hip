@@ -228,12 +228,17 @@ rt_status rt_scene_upload(const rt_scene_desc* d, void* stream, rt_scene* out) {
     off = align_up(off + bytes, 256);
     return o;
   };
-  size_t o_geom = take(N * sizeof(float4));
+  const size_t N4 = pad_spheres((int)N);
+  size_t o_geom = take((N4 + kGroup) * sizeof(float4));
   size_t o_rad = take(N * sizeof(float2));
   size_t o_mat = take((N + P) * sizeof(float4));
   size_t o_shine = take((N + P) * sizeof(float));
   size_t o_pgeom = take(P * sizeof(float4));
   size_t o_light = take(L * sizeof(float4));
+  size_t o_eye_cone = take((N4 + kGroup) * sizeof(float4));
+  size_t o_light_cone = take((L * N4 + kGroup) * sizeof(float4));
+  size_t o_refl = take((N4 + kGroup) * sizeof(float4));
+  size_t o_consts = take(2 * sizeof(float4));
   sc->staging_floats = 9 * N + 9 * P + 4 * L;
   size_t o_stage = take(sc->staging_floats * sizeof(float));
   size_t o_part = take((size_t)blocks * sc->grad_stride * sizeof(float));
@@ -251,6 +256,10 @@ rt_status rt_scene_upload(const rt_scene_desc* d, void* stream, rt_scene* out) {
   sc->shine = (float*)(base + o_shine);
   sc->pgeom = (float4*)(base + o_pgeom);
   sc->light = (float4*)(base + o_light);
+  sc->eye_cone = (float4*)(base + o_eye_cone);
+  sc->light_cone = (float4*)(base + o_light_cone);
+  sc->refl = (float4*)(base + o_refl);
+  sc->consts = (float4*)(base + o_consts);
   sc->staging = (float*)(base + o_stage);
   sc->partials = (float*)(base + o_part);
   st = upload_values(sc, d, (hipStream_t)stream);
@@ -296,14 +305,25 @@ static rt_status check_records(const rt_records* rec, int32_t W, int32_t H, int3
 
 rt_status rt_render(rt_scene sc, const rt_camera* cam, int32_t W, int32_t H, int32_t depth,
                     float* rgb_out, int32_t* id_out, const rt_records* rec, void* stream) {
+  return rt_render_ex(sc, cam, W, H, depth, rgb_out, id_out, rec, 0, stream);
+}
+
+rt_status rt_render_ex(rt_scene sc, const rt_camera* cam, int32_t W, int32_t H, int32_t depth,
+                       float* rgb_out, int32_t* id_out, const rt_records* rec, uint32_t flags,
+                       void* stream) {
   if (!sc) return fail(RT_ERR_INVALID_ARG, "scene is NULL");
+  if (flags & ~(uint32_t)RT_RENDER_NO_PREFILTER)
+    return fail(RT_ERR_INVALID_ARG, "unknown render flags 0x%x", flags);
   rt_status st = validate_camera(cam, W, H, depth);
   if (st != RT_OK) return st;
   if (!rgb_out) return fail(RT_ERR_INVALID_ARG, "rgb_out is NULL");
   if ((st = check_records(rec, W, H, depth)) != RT_OK) return st;
   CameraDev c = camera_dev(*cam, W, H);
-  hipError_t e = launch_render(sc->view(), c, depth, rgb_out, id_out, rec ? rec->ids : nullptr,
-                               rec ? rec->lit : nullptr, (hipStream_t)stream);
+  hipError_t e = launch_eye_cones(*sc, c, (hipStream_t)stream);
+  if (e == hipSuccess)
+    e = launch_render(sc->view(), c, depth, rgb_out, id_out, rec ? rec->ids : nullptr,
+                      rec ? rec->lit : nullptr, !(flags & RT_RENDER_NO_PREFILTER),
+                      (hipStream_t)stream);
   return hip_fail(e, "render launch");
 }
 
@@ -314,8 +334,9 @@ rt_status rt_render_counts(rt_scene sc, const rt_camera* cam, int32_t W, int32_t
   if (st != RT_OK) return st;
   if (!counts) return fail(RT_ERR_INVALID_ARG, "counts is NULL");
   CameraDev c = camera_dev(*cam, W, H);
-  hipError_t e = launch_counts(sc->view(), c, depth, (unsigned long long*)counts,
-                               (hipStream_t)stream);
+  hipError_t e = launch_eye_cones(*sc, c, (hipStream_t)stream);
+  if (e == hipSuccess)
+    e = launch_counts(sc->view(), c, depth, (unsigned long long*)counts, (hipStream_t)stream);
   return hip_fail(e, "count launch");
 }
 
@@ -332,8 +353,10 @@ rt_status rt_render_backward(rt_scene sc, const rt_camera* cam, int32_t W, int32
     return fail(RT_ERR_UNSUPPORTED, "rt_render_backward supports at most 2335 spheres, scene has %d",
                 sc->n_spheres);
   CameraDev c = camera_dev(*cam, W, H);
-  hipError_t e = launch_backward(*sc, c, depth, grad_rgb, rec ? rec->ids : nullptr,
-                                 rec ? rec->lit : nullptr, *grads, (hipStream_t)stream);
+  hipError_t e = rec ? hipSuccess : launch_eye_cones(*sc, c, (hipStream_t)stream);
+  if (e == hipSuccess)
+    e = launch_backward(*sc, c, depth, grad_rgb, rec ? rec->ids : nullptr,
+                        rec ? rec->lit : nullptr, *grads, (hipStream_t)stream);
   return hip_fail(e, "backward launch");
 }
 

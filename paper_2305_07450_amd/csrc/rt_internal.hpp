@@ -19,12 +19,16 @@ struct rt_scene_s {
   float ambient = 0, spec_strength = 0, t_min = 0, bg[3] = {0, 0, 0};
   void* buffer = nullptr;  // single hipMalloc
   size_t bytes = 0;
-  float4* geom = nullptr;  // [N]   cx cy cz r^2
+  float4* geom = nullptr;  // [n4+kGroup] cx cy cz r^2 (padding spheres: r^2 = -1)
   float2* rad = nullptr;   // [N]   r, 1/r
   float4* mat = nullptr;   // [N+P] albedo, kr
   float* shine = nullptr;  // [N+P]
   float4* pgeom = nullptr; // [P]
   float4* light = nullptr; // [L]
+  float4* eye_cone = nullptr;    // [n4+kGroup] rebuilt for the camera of each call
+  float4* light_cone = nullptr;  // [L*n4 + kGroup]  rows of n4, rebuilt by every upload/update
+  float4* refl = nullptr;        // [n4+kGroup] mirror-ray prefilter table
+  float4* consts = nullptr;      // [2] scene centre, max radius, max centre distance
   float* staging = nullptr;     // raw copy of host desc arrays
   size_t staging_floats = 0;
   float* partials = nullptr;    // adjoint partials [kAdjointBlocks][grad_stride]
@@ -33,6 +37,9 @@ struct rt_scene_s {
   rtk::SceneDev view() const {
     rtk::SceneDev s;
     s.geom = geom; s.rad = rad; s.mat = mat; s.shine = shine; s.pgeom = pgeom; s.light = light;
+    s.eye_cone = eye_cone; s.light_cone = light_cone;
+    s.refl = refl; s.consts = consts;
+    s.n4 = rtk::pad_spheres(n_spheres);
     s.n_spheres = n_spheres; s.n_planes = n_planes; s.n_lights = n_lights;
     s.spec_model = spec_model;
     s.ambient = ambient; s.spec_strength = spec_strength; s.t_min = t_min;
@@ -63,8 +70,12 @@ struct RawScene {
 
 hipError_t launch_pack(const rt_scene_s& sc, const RawScene& raw, hipStream_t stream);
 
+// Cones of every sphere seen from the camera's eye, into sc.eye_cone.
+hipError_t launch_eye_cones(const rt_scene_s& sc, const CameraDev& c, hipStream_t stream);
+
 hipError_t launch_render(const SceneDev& s, const CameraDev& c, int depth, float* rgb,
-                         int32_t* ids, int32_t* rec_ids, uint8_t* rec_lit, hipStream_t stream);
+                         int32_t* ids, int32_t* rec_ids, uint8_t* rec_lit, bool prefilter,
+                         hipStream_t stream);
 
 hipError_t launch_counts(const SceneDev& s, const CameraDev& c, int depth,
                          unsigned long long* counts, hipStream_t stream);

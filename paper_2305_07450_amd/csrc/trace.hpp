@@ -35,10 +35,63 @@ struct SceneDev {
   const float* shine;    // [N+P] specular exponent
   const float4* pgeom;   // [P]   unit normal m, offset h
   const float4* light;   // [L]   position, intensity
+  const float4* eye_cone;    // [N]    cone of each sphere seen from the eye
+  const float4* light_cone;  // [L][N] cone of each sphere seen from each light
+  const float4* refl;        // [N]    (c - C, K) for the mirror-ray prefilter
+  const float4* consts;      // [2]    (C, max r), (max |c - C|, 0, 0, 0)
   int n_spheres, n_planes, n_lights, spec_model;
+  int n4;   // sphere tables padded to a multiple of kGroup (+kGroup for prefetch)
   float ambient, spec_strength, t_min;
   float bg_r, bg_g, bg_b;
 };
+
+// Sphere tables (geom, eye_cone, light_cone) hold n4 = round_up(N, kGroup)
+// entries plus one more group, so the loops below read kGroup spheres with
+// two 64-byte scalar loads and fetch the next group while testing the current
+// one.  Padding spheres can never pass: r^2 = -1 and cone threshold 2.
+constexpr int kGroup = 8;
+constexpr float kPadConeW = 2.0f;
+constexpr float kPadR2 = -1.0f;
+
+__host__ __device__ constexpr int pad_spheres(int n) { return (n + kGroup - 1) / kGroup * kGroup; }
+
+// Mirror rays start anywhere, so they get a cheaper conservative test in the
+// classic form Delta = b^2 - |oc|^2 + r^2 evaluated about the scene centre C
+// (c' = c - C, o' = o - C, b = (c' - o').d):
+//   e = b^2 - (K - 2 c'.o'),   K = |c'|^2 - r^2 - G |c'|^2,
+// and the sphere is a candidate iff e >= (1 - G) |o'|^2, i.e. Delta >= -M
+// with M = G (|c'|^2 + |o'|^2), and b >= -(max r) - slack (not wholly behind
+// the origin).  That form cancels, but its FP32 error is at most about
+// 26 u (|c'|^2 + |o'|^2) (u = 2^-24); G = 128 u keeps M well above it (an
+// FP32 emulation over 12M random near-tangent pairs used under 10% of M).
+// Candidates run the exact test, so the image is the exact test's.
+constexpr float kReflGamma = 128.0f * 5.9604644775390625e-08f;
+constexpr float kReflSlack = 16.0f * 5.9604644775390625e-08f;
+
+// Cone of a sphere seen from a point q (the eye, or a light): unit axis a
+// towards the centre and a threshold w such that every unit direction u with
+// a.u < w misses the sphere.  A ray from q meets a sphere of radius r at
+// distance D iff the angle to the axis is at most asin(r/D), i.e.
+// a.u >= cos(theta) = sqrt(1 - r^2/D^2); w lowers cos(theta) by more than the
+// FP32 error of both this test and the exact test that follows it, so the
+// cone test only skips spheres the exact test would reject.  (The exact test
+// accepts only if sin(angle) <= (r + O(eps D)) / D, i.e. cos(angle) >=
+// cos(theta) - O(eps (r/D) / cos(theta)); the margin below is 32x that bound
+// plus the rounding of the 3-term dot product and of the table.)  A point
+// within 0.5% of a sphere's surface or inside it gets w = -2: every direction
+// is a candidate.  Built in double, rounded once.
+__device__ __forceinline__ float4 sphere_cone(double qx, double qy, double qz, double cx,
+                                              double cy, double cz, double r) {
+  const double eps = 1.1920928955078125e-07;   // 2^-23
+  double vx = cx - qx, vy = cy - qy, vz = cz - qz;
+  double D2 = vx * vx + vy * vy + vz * vz;
+  double s2 = r * r / D2;
+  double c2 = 1.0 - s2;
+  if (!(c2 > 0.01)) return make_float4(0.0f, 0.0f, 0.0f, -2.0f);
+  double D = sqrt(D2), c = sqrt(c2);
+  double w = c - 64.0 * eps * sqrt(s2) / c - 16.0 * eps;
+  return make_float4((float)(vx / D), (float)(vy / D), (float)(vz / D), (float)w);
+}
 
 // Camera basis, made on the host in double: right = R e_x, up = R e_y,
 // fwd = R (0, 0, -b) with b = 1/tan(fov/2) and R = Ry(yaw) Rx(pitch).
@@ -68,10 +121,28 @@ __device__ __forceinline__ float2 ld2(const float2* base, int i) {
 __device__ __forceinline__ float ld1(const float* base, int i) {
   return ((const RT_CONSTANT float*)base)[i];
 }
+typedef float rt_v16 __attribute__((ext_vector_type(16)));
+// Four consecutive float4 from index i (a multiple of 4) in one scalar load.
+__device__ __forceinline__ rt_v16 ld16(const float4* base, int i) {
+  return ((const RT_CONSTANT rt_v16*)base)[i >> 2];
+}
+
+// 1-ulp hardware square root and reciprocal square root.  All kernels use
+// these same functions, so every launch shape rounds the same way.
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
 
 struct Ray {
   float ox, oy, oz;
   float dx, dy, dz;
+};
+
+// Surface point of a hit: position, outward normal, material, primitive id.
+struct Surface {
+  float px, py, pz;
+  float nx, ny, nz;
+  float ar, ag, ab, kr, shine;
+  int id;
 };
 
 __device__ __forceinline__ float dot3(float ax, float ay, float az, float bx, float by, float bz) {
@@ -87,7 +158,7 @@ __device__ __forceinline__ Ray primary_ray(const CameraDev& c, int x, int y) {
   float dx = fmaf(u, c.rx, fmaf(v, c.ux, c.fx));
   float dy = fmaf(u, c.ry, fmaf(v, c.uy, c.fy));
   float dz = fmaf(u, c.rz, fmaf(v, c.uz, c.fz));
-  float inv = 1.0f / __builtin_sqrtf(dot3(dx, dy, dz, dx, dy, dz));
+  float inv = frsq(dot3(dx, dy, dz, dx, dy, dz));
   Ray r;
   r.ox = c.ex; r.oy = c.ey; r.oz = c.ez;
   r.dx = dx * inv; r.dy = dy * inv; r.dz = dz * inv;
@@ -113,7 +184,7 @@ __device__ __forceinline__ float sphere_ff(float4 g, const Ray& r, float& b) {
 // Nearest root above t_min (the far root when the near one is not), or +inf.
 // Requires ff <= r^2.
 __device__ __forceinline__ float sphere_root(float r2, float ff, float b, float t_min) {
-  float sq = __builtin_sqrtf(r2 - ff);
+  float sq = fsqrt(r2 - ff);
   float t0 = -b - sq;
   float t1 = -b + sq;
   return t0 > t_min ? t0 : (t1 > t_min ? t1 : __builtin_inff());
@@ -150,22 +221,93 @@ struct Count {
 // plane a mirror ray leaves (-1 otherwise): a ray reflected off a plane moves
 // away from it and never meets it again, so that plane is not tested; this
 // keeps FP32 rounding of the start point from re-hitting it at grazing angles.
+//
+// Primary rays (kFromEye) all start at the eye, so each sphere is first
+// tested against its cone seen from the eye (3 FMA-class ops and a compare);
+// only directions inside the cone run the exact test.  The exact test is the
+// same code in both paths, so both give the same bits.
+// True when any active lane of the wave passes: a branch on it is taken or
+// skipped by the whole wave, so no exec mask is saved or restored, and the
+// per-lane effect inside is applied with selects.
+__device__ __forceinline__ bool wave_any(bool p) { return __builtin_amdgcn_ballot_w64(p) != 0; }
+
+// Exact test of sphere i (geometry g) against the ray; keeps the nearest.
+__device__ __forceinline__ void test_sphere(float4 g, int i, const Ray& r, float tmin,
+                                            float& t_best, int& id_best) {
+  float b;
+  float ff = sphere_ff(g, r, b);
+  const bool in = ff <= g.w;
+  if (wave_any(in)) {
+    // lanes that miss compute a harmless root and are masked by `better`
+    float t = sphere_root(g.w, in ? ff : g.w, b, tmin);
+    const bool better = in && t < t_best;
+    t_best = better ? t : t_best;
+    id_best = better ? i : id_best;
+  }
+}
+
+__device__ __forceinline__ float4 part(const rt_v16& v, int k) {
+  return make_float4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
+}
+
+// a.u - w for a cone (a, w): >= 0 inside the cone (with the cone's margin).
+__device__ __forceinline__ float cone_excess(float4 a, float ux, float uy, float uz) {
+  return fmaf(a.x, ux, fmaf(a.y, uy, fmaf(a.z, uz, -a.w)));
+}
+
+template <bool kFromEye = false, bool kPrefilter = true>
 __device__ __forceinline__ void closest_hit(const SceneDev& s, const Ray& r, float& t_best,
                                             int& id_best, int from_plane = -1) {
   t_best = __builtin_inff();
   id_best = kMiss;
   const float tmin = s.t_min;
-#pragma unroll 4
-  for (int i = 0; i < s.n_spheres; ++i) {
-    float4 g = ld4(s.geom, i);
-    float b;
-    float ff = sphere_ff(g, r, b);
-    if (ff <= g.w) {
-      float t = sphere_root(g.w, ff, b, tmin);
-      if (t < t_best) {
-        t_best = t;
-        id_best = i;
+  if (kFromEye && kPrefilter) {
+    // the exact test runs for every lane once any lane is inside the cone, so
+    // the result is the exact test's whatever the cone decides
+    rt_v16 c0 = ld16(s.eye_cone, 0), c1 = ld16(s.eye_cone, 4);
+    for (int i = 0; i < s.n4; i += kGroup) {
+      rt_v16 n0 = ld16(s.eye_cone, i + 8), n1 = ld16(s.eye_cone, i + 12);
+#pragma unroll
+      for (int k = 0; k < kGroup; ++k) {
+        float4 a = part(k < 4 ? c0 : c1, k & 3);
+        if (wave_any(cone_excess(a, r.dx, r.dy, r.dz) >= 0.0f))
+          test_sphere(ld4(s.geom, i + k), i + k, r, tmin, t_best, id_best);
       }
+      c0 = n0;
+      c1 = n1;
+    }
+  } else if (kPrefilter) {
+    const float4 k0 = ld4(s.consts, 0), k1 = ld4(s.consts, 1);
+    const float opx = r.ox - k0.x, opy = r.oy - k0.y, opz = r.oz - k0.z;
+    const float od = dot3(opx, opy, opz, r.dx, r.dy, r.dz);
+    const float m2x = -2.0f * opx, m2y = -2.0f * opy, m2z = -2.0f * opz;
+    const float oo = dot3(opx, opy, opz, opx, opy, opz);
+    const float thr_e = oo * (1.0f - kReflGamma);
+    const float thr_b = -(k0.w + kReflSlack * (k1.x + fmaxf(1.0f, oo)));
+    rt_v16 c0 = ld16(s.refl, 0), c1 = ld16(s.refl, 4);
+    for (int i = 0; i < s.n4; i += kGroup) {
+      rt_v16 n0 = ld16(s.refl, i + 8), n1 = ld16(s.refl, i + 12);
+#pragma unroll
+      for (int k = 0; k < kGroup; ++k) {
+        float4 a = part(k < 4 ? c0 : c1, k & 3);
+        float bb = fmaf(a.x, r.dx, fmaf(a.y, r.dy, fmaf(a.z, r.dz, -od)));
+        float q = fmaf(a.x, m2x, fmaf(a.y, m2y, fmaf(a.z, m2z, a.w)));
+        float e = fmaf(bb, bb, -q);
+        if (wave_any(e >= thr_e && bb >= thr_b))
+          test_sphere(ld4(s.geom, i + k), i + k, r, tmin, t_best, id_best);
+      }
+      c0 = n0;
+      c1 = n1;
+    }
+  } else {
+    rt_v16 c0 = ld16(s.geom, 0), c1 = ld16(s.geom, 4);
+    for (int i = 0; i < s.n4; i += kGroup) {
+      rt_v16 n0 = ld16(s.geom, i + 8), n1 = ld16(s.geom, i + 12);
+#pragma unroll
+      for (int k = 0; k < kGroup; ++k)
+        test_sphere(part(k < 4 ? c0 : c1, k & 3), i + k, r, tmin, t_best, id_best);
+      c0 = n0;
+      c1 = n1;
     }
   }
   for (int j = 0; j < s.n_planes; ++j) {
@@ -177,31 +319,64 @@ __device__ __forceinline__ void closest_hit(const SceneDev& s, const Ray& r, flo
   }
 }
 
-// Shadow ray from p towards a light at distance `dist`: blocked iff some
-// primitive has a root in (t_min, dist).  Each lane stops at its first
-// occluder; the wave stops when all its lanes have.
-template <class Cnt>
-__device__ __forceinline__ bool occluded(const SceneDev& s, const Ray& r, float dist, int self,
-                                         Cnt& cnt) {
-  // `self` is the primitive the ray leaves.  A shadow ray is only traced when
-  // n.l > 0, i.e. it leaves that convex surface outwards and cannot meet it
-  // again, so its test is skipped: in exact arithmetic it never occludes, and
-  // skipping it keeps FP32 rounding of the start point from re-hitting it.
-  const float tmin = s.t_min;
-#pragma unroll 4
-  for (int i = 0; i < s.n_spheres; ++i) {
-    float4 g = ld4(s.geom, i);
-    float b;
-    float ff = sphere_ff(g, r, b);
-    if (ff <= g.w && i != self) {
-      if (sphere_root(g.w, ff, b, tmin) < dist) {
-        cnt.tests(i + 1, 0);
-        return true;
+// Shadow ray between a surface point p and light l at distance `dist`
+// (direction l_dir from p to the light): blocked iff some primitive has a
+// root in (t_min, dist) along the ray from p.  Spheres are tested on the
+// reversed ray from the light, u = -l_dir, where that interval becomes
+// (0, dist - t_min): every shadow ray towards light l shares that origin, so
+// a sphere is first tested against its cone seen from the light and only
+// directions inside the cone run the exact root test.  Each lane stops at its
+// first occluder (ascending id order); the wave stops when all its lanes have.
+//
+// `self` is the primitive p lies on.  A shadow ray is only traced when
+// n.l > 0, i.e. it leaves that convex surface outwards and cannot meet it
+// again, so its test is skipped: in exact arithmetic it never occludes, and
+// skipping it keeps FP32 rounding of p from re-hitting it.
+template <bool kPrefilter, class Cnt>
+__device__ __forceinline__ bool occluded(const SceneDev& s, int l, float4 q, const Surface& f,
+                                         float lx, float ly, float lz, float dist, Cnt& cnt) {
+  const float lim = dist - s.t_min;
+  const float ux = -lx, uy = -ly, uz = -lz;
+  const float4* cones = s.light_cone + (int64_t)l * s.n4;
+  const int self = f.id;
+  bool occ = false;
+  int first = 0;   // first occluding sphere, for the work counters
+  Ray rr;
+  rr.ox = q.x; rr.oy = q.y; rr.oz = q.z;
+  rr.dx = ux; rr.dy = uy; rr.dz = uz;
+  rt_v16 c0 = ld16(cones, 0), c1 = ld16(cones, 4);
+  for (int i = 0; i < s.n4; i += kGroup) {
+    rt_v16 n0 = ld16(cones, i + 8), n1 = ld16(cones, i + 12);
+#pragma unroll
+    for (int k = 0; k < kGroup; ++k) {
+      float4 a = part(k < 4 ? c0 : c1, k & 3);
+      if (!kPrefilter || wave_any(!occ && cone_excess(a, ux, uy, uz) >= 0.0f)) {
+        float4 g = ld4(s.geom, i + k);
+        float b;
+        float ff = sphere_ff(g, rr, b);
+        const bool in = !occ && ff <= g.w && i + k != self;
+        if (wave_any(in)) {
+          float sq = fsqrt(in ? g.w - ff : 0.0f);
+          float t0 = -b - sq, t1 = -b + sq;
+          const bool hit = in && ((t0 > 0.0f && t0 < lim) || (t1 > 0.0f && t1 < lim));
+          first = hit ? i + k : first;
+          occ = occ || hit;
+        }
       }
     }
+    c0 = n0;
+    c1 = n1;
+    if (!wave_any(!occ)) break;   // every lane of the wave is occluded
   }
+  if (occ) {
+    cnt.tests(first + 1, 0);
+    return true;
+  }
+  Ray sr;
+  sr.ox = f.px; sr.oy = f.py; sr.oz = f.pz;
+  sr.dx = lx; sr.dy = ly; sr.dz = lz;
   for (int j = 0; j < s.n_planes; ++j)
-    if (s.n_spheres + j != self && plane_root(ld4(s.pgeom, j), r, tmin) < dist) {
+    if (s.n_spheres + j != self && plane_root(ld4(s.pgeom, j), sr, s.t_min) < dist) {
       cnt.tests(s.n_spheres, j + 1);
       return true;
     }
@@ -214,13 +389,6 @@ __device__ __forceinline__ float spec_pow(float x, float e) {
   return x > 0.0f ? exp2f(e * log2f(x)) : 0.0f;
 }
 
-// Surface point of a hit: position, outward normal, material, primitive id.
-struct Surface {
-  float px, py, pz;
-  float nx, ny, nz;
-  float ar, ag, ab, kr, shine;
-  int id;
-};
 
 __device__ __forceinline__ Surface surface_at(const SceneDev& s, const Ray& r, float t, int id) {
   Surface f;
@@ -234,7 +402,7 @@ __device__ __forceinline__ Surface surface_at(const SceneDev& s, const Ray& r, f
     // point does not grow from bounce to bounce
     float4 g = ld4(s.geom, id);
     float vx = f.px - g.x, vy = f.py - g.y, vz = f.pz - g.z;
-    float inv = 1.0f / __builtin_sqrtf(dot3(vx, vy, vz, vx, vy, vz));
+    float inv = frsq(dot3(vx, vy, vz, vx, vy, vz));
     f.nx = vx * inv;
     f.ny = vy * inv;
     f.nz = vz * inv;
@@ -262,12 +430,12 @@ __device__ __forceinline__ float spec_base(int model, float nx, float ny, float 
   }
   float hx = lx + vx, hy = ly + vy, hz = lz + vz;
   float hl2 = dot3(hx, hy, hz, hx, hy, hz);
-  return hl2 > 0.0f ? dot3(nx, ny, nz, hx, hy, hz) / __builtin_sqrtf(hl2) : 0.0f;
+  return hl2 > 0.0f ? dot3(nx, ny, nz, hx, hy, hz) * frsq(hl2) : 0.0f;
 }
 
 // Light terms at a surface point: A = k_a + sum I (n.l), S = sum I k_s spec,
 // over lights with n.l > 0 and no occluder; returns the lit-light mask.
-template <class Cnt>
+template <bool kPrefilter = true, class Cnt = NoCount>
 __device__ __forceinline__ uint32_t light_terms(const SceneDev& s, const Surface& f, const Ray& r,
                                                 float& A, float& S, Cnt& cnt) {
   A = s.ambient;
@@ -276,17 +444,16 @@ __device__ __forceinline__ uint32_t light_terms(const SceneDev& s, const Surface
   for (int l = 0; l < s.n_lights; ++l) {
     float4 q = ld4(s.light, l);
     float lx = q.x - f.px, ly = q.y - f.py, lz = q.z - f.pz;
-    float dist = __builtin_sqrtf(dot3(lx, ly, lz, lx, ly, lz));
-    lx = lx / dist;
-    ly = ly / dist;
-    lz = lz / dist;
+    float d2 = dot3(lx, ly, lz, lx, ly, lz);
+    float inv = frsq(d2);
+    float dist = d2 * inv;
+    lx *= inv;
+    ly *= inv;
+    lz *= inv;
     float nl = dot3(f.nx, f.ny, f.nz, lx, ly, lz);
     if (nl > 0.0f) {
-      Ray sr;
-      sr.ox = f.px; sr.oy = f.py; sr.oz = f.pz;
-      sr.dx = lx; sr.dy = ly; sr.dz = lz;
       cnt.ray(kCntShadow);
-      if (!occluded(s, sr, dist, f.id, cnt)) {
+      if (!occluded<kPrefilter>(s, l, q, f, lx, ly, lz, dist, cnt)) {
         lit |= 1u << l;
         A = fmaf(q.w, nl, A);
         float x = spec_base(s.spec_model, f.nx, f.ny, f.nz, lx, ly, lz, -r.dx, -r.dy, -r.dz, nl);
@@ -304,7 +471,7 @@ __device__ __forceinline__ void reflect_ray(Ray& r, const Surface& f) {
   float dx = fmaf(-dn2, f.nx, r.dx);
   float dy = fmaf(-dn2, f.ny, r.dy);
   float dz = fmaf(-dn2, f.nz, r.dz);
-  float inv = 1.0f / __builtin_sqrtf(dot3(dx, dy, dz, dx, dy, dz));
+  float inv = frsq(dot3(dx, dy, dz, dx, dy, dz));
   r.dx = dx * inv;
   r.dy = dy * inv;
   r.dz = dz * inv;
@@ -320,7 +487,7 @@ struct NoRecords {
 // The whole path of one pixel.  `sink.seg(k, id)` and `sink.lit(k, mask)` see
 // every traced segment; the caller marks untraced segments.  Returns the
 // number of segments traced.
-template <class Sink, class Cnt = NoCount>
+template <class Sink, class Cnt = NoCount, bool kPrefilter = true>
 __device__ __forceinline__ int trace_path(const SceneDev& s, Ray r, int depth, float& cr,
                                           float& cg, float& cb, int& prim, Sink& sink,
                                           Cnt&& cnt = Cnt()) {
@@ -332,7 +499,10 @@ __device__ __forceinline__ int trace_path(const SceneDev& s, Ray r, int depth, f
   for (; k <= depth; ++k) {
     float t;
     int id;
-    closest_hit(s, r, t, id, from_plane);
+    if (k == 0)
+      closest_hit<true, kPrefilter>(s, r, t, id);
+    else
+      closest_hit<false, kPrefilter>(s, r, t, id, from_plane);
     cnt.ray(k == 0 ? kCntPrimary : kCntReflection);
     cnt.tests(s.n_spheres, s.n_planes);
     if (k == 0) prim = id;
@@ -345,7 +515,7 @@ __device__ __forceinline__ int trace_path(const SceneDev& s, Ray r, int depth, f
     }
     Surface f = surface_at(s, r, t, id);
     float A, S;
-    sink.lit(k, light_terms(s, f, r, A, S, cnt));
+    sink.lit(k, light_terms<kPrefilter>(s, f, r, A, S, cnt));
     if (k < depth) {
       float w = A * (1.0f - f.kr);
       cr = fmaf(T, fmaf(w, f.ar, S), cr);

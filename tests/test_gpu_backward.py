@@ -1,0 +1,153 @@
+"""Adjoint (rt_render_backward) against the FP64 reference gradient (GPU).
+
+The reference is oracle/grad_ref.py: the fixed-visibility re-shade in torch
+float64 on the oracle's own records, pinned by central differences of the C
+oracle (tests/test_oracle_grad.py).  Both sides get the same dLoss/dRGB,
+non-zero only on pixels where the GPU's records equal the oracle's, that the
+oracle classifies well conditioned, and that are at least 2 px from a
+primary-id edge.  Bar: relative L2 error per parameter group <= 1e-3.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import scenegen
+from scenegen import Camera, SPEC_BLINN, SPEC_PHONG
+
+from .gpu_common import log
+
+pytestmark = pytest.mark.gpu
+
+GROUPS = ("albedo", "refl", "center", "light_pos", "light_int")
+REL_TOL = 1e-3
+
+
+@pytest.fixture(scope="module")
+def rt():
+    assert torch.cuda.is_available(), "GPU test without a GPU"
+    import paper_2305_07450_amd as rt
+    return rt
+
+
+def _alloc(scene):
+    N, L = scene.n_spheres, scene.n_lights
+    shapes = dict(albedo=(N, 3), refl=(N,), center=(N, 3), light_pos=(L, 3), light_int=(L,))
+    return {k: torch.full(s, float("nan"), device="cuda") for k, s in shapes.items()}
+
+
+def run_gpu(rt, scene, cam, W, H, D, target_rgb=None, grad_rgb=None, mode="checkpoint"):
+    with rt.SceneHandle(scene) as h:
+        rgb, ids, rec = rt.render(h.handle, cam, W, H, D, ids=True, records=True)
+        torch.cuda.synchronize()
+        out = dict(rgb=rgb.cpu().numpy().reshape(-1, 3).astype(np.float64),
+                   seg=rec.ids.cpu().numpy().reshape(D + 1, -1).T,
+                   lit=rec.lit.cpu().numpy().reshape(D + 1, -1).T.astype(np.uint32))
+        if grad_rgb is not None:
+            g = _alloc(scene)
+            gt = torch.tensor(grad_rgb.reshape(H, W, 3), dtype=torch.float32, device="cuda")
+            rt.rt_render_backward(h.handle, cam, W, H, D, gt, g,
+                                  rec if mode == "checkpoint" else None)
+            torch.cuda.synchronize()
+            out["grads"] = {k: v.cpu().numpy().astype(np.float64) for k, v in g.items()}
+    return out
+
+
+def reference_check(rt, oracle_mod, scene, cam, W, H, D, target, label):
+    from oracle import grad_ref
+    fwd = run_gpu(rt, scene, cam, W, H, D)
+    base = oracle_mod.render(scene, cam, W, H, D)
+    ok = oracle_mod.condition(scene, cam, W, H, D, base=base)
+    same = (fwd["seg"] == base.seg_id).all(1) & (fwd["lit"] == base.lit).all(1)
+    mask = same & ok & ~oracle_mod.id_edges(base.prim_id, W, H, 2)
+    tgt = oracle_mod.render(target, cam, W, H, D, records=False, margins=False).rgb
+    grad_rgb = 2.0 * (fwd["rgb"] - tgt) * mask[:, None]
+    grad_rgb = grad_rgb.astype(np.float32).astype(np.float64)
+    res = {}
+    for mode in ("checkpoint", "recompute"):
+        res[mode] = run_gpu(rt, scene, cam, W, H, D, grad_rgb=grad_rgb, mode=mode)["grads"]
+    o0, d0 = oracle_mod.camera_rays(cam, W, H, np.arange(W * H))
+    ref = grad_ref.vjp(scene, o0, d0, base.seg_id, base.lit, D, grad_rgb)
+    errs = {}
+    for k in GROUPS:
+        g = res["checkpoint"][k]
+        assert np.isfinite(g).all(), k
+        assert np.array_equal(g, res["recompute"][k]), f"{k}: checkpoint and recompute differ"
+        denom = max(np.linalg.norm(ref[k]), 1e-30)
+        errs[k] = float(np.linalg.norm(g - ref[k]) / denom)
+    log("grad parity", label, "mask", float(mask.mean()), errs)
+    for k in GROUPS:
+        assert errs[k] <= REL_TOL, (label, k, errs[k])
+    return res["checkpoint"], ref, mask, grad_rgb
+
+
+@pytest.mark.parametrize("model,seed", [(SPEC_BLINN, 0), (SPEC_PHONG, 1), (SPEC_BLINN, 2)])
+def test_small_scene_against_reference(rt, oracle_mod, model, seed):
+    W, H, D = 96, 54, 3
+    rng = np.random.default_rng(seed)
+    s = scenegen.random_scene(rng, 8, 2, spec_model=model)
+    target = scenegen.perturb_scene(s, np.random.default_rng(seed + 50))
+    reference_check(rt, oracle_mod, s, Camera(), W, H, D, target, f"small seed={seed}")
+
+
+def test_workload4_against_reference(rt, oracle_mod):
+    """1280x720, 128 spheres, 1 light, depth 3; target from N(0, 0.05) perturbed parameters."""
+    prob = scenegen.make_diff_problem()
+    wl = prob.workload
+    reference_check(rt, oracle_mod, wl.scene, wl.camera, wl.W, wl.H, wl.depth,
+                    prob.target_scene, wl.name)
+
+
+def test_deterministic_and_ragged(rt, oracle_mod):
+    """Two runs give identical bits; a ragged image size and depth 0/4 work."""
+    for (W, H, D) in ((37, 23, 0), (50, 29, 4)):
+        s = scenegen.tiny_scene(11, n_spheres=7, n_lights=2)
+        g = np.random.default_rng(3).normal(size=(W * H, 3))
+        a = run_gpu(rt, s, Camera(), W, H, D, grad_rgb=g)["grads"]
+        b = run_gpu(rt, s, Camera(), W, H, D, grad_rgb=g, mode="recompute")["grads"]
+        c = run_gpu(rt, s, Camera(), W, H, D, grad_rgb=g)["grads"]
+        for k in GROUPS:
+            assert np.array_equal(a[k], b[k]) and np.array_equal(a[k], c[k]), k
+
+
+def test_autograd_function_matches_direct_call(rt, oracle_mod):
+    from paper_2305_07450_amd.autograd import FixedParts, render_differentiable
+    W, H, D = 64, 36, 2
+    s = scenegen.tiny_scene(5, n_spheres=6, n_lights=1)
+    target = scenegen.perturb_scene(s, np.random.default_rng(9))
+    tgt = torch.tensor(oracle_mod.render(target, Camera(), W, H, D, records=False,
+                                         margins=False).rgb.reshape(H, W, 3),
+                       dtype=torch.float32, device="cuda")
+    f = lambda a: torch.tensor(np.asarray(a), dtype=torch.float32, device="cuda",
+                               requires_grad=True)
+    params = [f(s.sphere_mat[:, :3]), f(s.sphere_mat[:, 3]), f(s.sphere_geom[:, :3]),
+              f(s.light[:, :3]), f(s.light[:, 3])]
+    with rt.SceneHandle(s) as h:
+        fixed = FixedParts(s)
+        for mode in ("checkpoint", "recompute"):
+            for p in params:
+                p.grad = None
+            img = render_differentiable(*params, fixed, h.handle, Camera(), W, H, D, mode=mode)
+            loss = ((img - tgt) ** 2).sum()
+            loss.backward()
+            grad_rgb = (2 * (img.detach() - tgt)).cpu().numpy().reshape(-1, 3)
+            direct = run_gpu(rt, s, Camera(), W, H, D, grad_rgb=grad_rgb)["grads"]
+            for p, k in zip(params, GROUPS):
+                assert np.array_equal(p.grad.cpu().numpy(), direct[k].astype(np.float32)), (mode, k)
+
+
+def test_record_budget_zero_forces_recompute(rt, monkeypatch):
+    from paper_2305_07450_amd import autograd as ag
+    monkeypatch.setenv("RT_RECORD_BUDGET_BYTES", "0")
+    assert ag.record_budget() == 0
+    s = scenegen.tiny_scene(5, n_spheres=4, n_lights=1)
+    f = lambda a: torch.tensor(np.asarray(a), dtype=torch.float32, device="cuda",
+                               requires_grad=True)
+    params = [f(s.sphere_mat[:, :3]), f(s.sphere_mat[:, 3]), f(s.sphere_geom[:, :3]),
+              f(s.light[:, :3]), f(s.light[:, 3])]
+    with rt.SceneHandle(s) as h:
+        img = ag.render_differentiable(*params, ag.FixedParts(s), h.handle, Camera(), 32, 18, 2)
+        assert img.grad_fn is not None
+        img.sum().backward()
+        assert img.grad_fn is not None
+    assert all(torch.isfinite(p.grad).all() for p in params)

@@ -115,3 +115,62 @@ def test_lambert_gradient_closed_form(oracle_mod):
         want = np.zeros(3)
         want[c] = float(s.ambient) + 0.75 * nl
         assert np.allclose(grads["albedo"][0], want, atol=1e-13)
+
+
+def test_directional_derivatives_at_workload4_scale(oracle_mod):
+    """Three random directional derivatives of the masked loss for the
+    1280x720, 128-sphere, depth-3 workload (every 8th row): autograd of the
+    re-shade vs Richardson-refined central differences of the C oracle.
+
+    Kept pixels: well conditioned, records unchanged at every perturbed point,
+    and smooth at the step sizes used (per-pixel Richardson estimates from
+    steps h and h/2 agree).  Chaotic multi-bounce pixels and segments close to
+    a sphere's silhouette have colour derivatives in the hundreds or kinks
+    narrower than h; they need far smaller steps.  The filter never looks at
+    the analytic gradient."""
+    from oracle import Scene64, grad_ref
+    prob = scenegen.make_diff_problem()
+    wl = prob.workload
+    s, W, H, D = wl.scene, wl.W, wl.H, wl.depth
+    rows = np.arange(0, H, 8)
+    pix = (rows[:, None] * W + np.arange(W)[None, :]).reshape(-1)
+    base = oracle_mod.render(s, Camera(), W, H, D, pix)
+    tgt = oracle_mod.render(prob.target_scene, Camera(), W, H, D, pix, records=False,
+                            margins=False).rgb
+    o, d = oracle_mod.camera_rays(Camera(), W, H, pix)
+    mask = oracle_mod.condition(s, Camera(), W, H, D, pix, base=base)
+    rng = np.random.default_rng(17)
+    dirs = [{k: rng.normal(size=v.shape) for k, v in grad_ref.params_of(s, False).items()}
+            for _ in range(3)]
+    hs = (H_FD / 2, H_FD / 4, H_FD / 8)
+    per_dir = []
+    for dv in dirs:
+        rgb = {}
+        for h in hs:
+            for sg in (1, -1):
+                s2 = Scene64(s)
+                hh = sg * h
+                s2.sphere_mat[:, :3] += hh * dv["albedo"]
+                s2.sphere_mat[:, 3] += hh * dv["refl"]
+                s2.sphere_geom[:, :3] += hh * dv["center"]
+                s2.light[:, :3] += hh * dv["light_pos"]
+                s2.light[:, 3] += hh * dv["light_int"]
+                r = oracle_mod.render(s2, Camera(), W, H, D, pix, margins=False)
+                mask &= (r.seg_id == base.seg_id).all(1) & (r.lit == base.lit).all(1)
+                rgb[hh] = r.rgb
+        dc = [(rgb[h] - rgb[-h]) / (2 * h) for h in hs]          # per-pixel dC/dh
+        r1 = (4 * dc[1] - dc[0]) / 3
+        r2 = (4 * dc[2] - dc[1]) / 3
+        mask &= (np.abs(r1 - r2) <= 1e-6 + 1e-4 * np.abs(r2)).all(1)
+        per_dir.append(rgb)
+    assert mask.mean() > 0.5
+    loss, grads, _ = grad_ref.masked_loss_grad(s, o, d, base.seg_id, base.lit, D, tgt, mask)
+    m = mask[:, None]
+    L = lambda c: (((c - tgt) * m) ** 2).sum()
+    for dv, rgb in zip(dirs, per_dir):
+        h1, h2 = hs[0], hs[1]
+        d1 = (L(rgb[h1]) - L(rgb[-h1])) / (2 * h1)
+        d2 = (L(rgb[h2]) - L(rgb[-h2])) / (2 * h2)
+        fd = (4 * d2 - d1) / 3
+        an = sum(float((grads[k] * dv[k]).sum()) for k in grads)
+        assert abs(fd - an) <= 1e-5 * max(abs(fd), 1e-12), (fd, an)
