@@ -243,6 +243,15 @@ def main():
                      "kernel_ms": round(ms_kernel, 5),
                      "flops_per_launch": flops},
     }
+    if not args.no_extras:
+        # the same image through the kernel variants kept for comparison
+        variants = {}
+        for name, flags in (("no_prefilter", rt.RT_RENDER_NO_PREFILTER),):
+            ms = time_gpu(lambda: rt.rt_render_ex(h.handle, wl.camera, W, H, D, rgb, None, None,
+                                                  flags, stream), 20, 3, stream)
+            variants[name] = {"ms": round(ms, 4),
+                              "tflops_algorithmic": round(flops / (ms * 1e-3) / 1e12, 2)}
+        out["variants"] = variants
     h.close()
     if not args.no_extras:
         out["fwd_bwd"] = bench_fwd_bwd(rt, scenegen, stream, 20)

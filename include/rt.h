@@ -149,13 +149,13 @@ rt_status rt_render(rt_scene scene, const rt_camera* cam, int32_t W, int32_t H, 
                     float* rgb_out, int32_t* id_out, const rt_records* rec, void* stream);
 
 /* Flags of rt_render_ex. */
-#define RT_RENDER_NO_PREFILTER 1u  /* run the exact ray-primitive test on every
-                                      pair: the cheap tests that skip pairs
-                                      (cones from the eye and the lights, the
-                                      mirror-ray bound) only skip pairs the
-                                      exact test rejects, so the image is the
-                                      same bits either way; this flag exists
-                                      to check that */
+#define RT_RENDER_NO_PREFILTER 1u  /* run the exact ray-sphere test on every
+                                      pair: the cone tests that skip pairs
+                                      (cones seen from the eye and from the
+                                      lights) only skip pairs the exact test
+                                      rejects, so the image is the same bits
+                                      either way; this flag exists to check
+                                      that */
 
 /* rt_render with flags (0 = rt_render). */
 rt_status rt_render_ex(rt_scene scene, const rt_camera* cam, int32_t W, int32_t H, int32_t depth,

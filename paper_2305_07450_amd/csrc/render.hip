@@ -138,77 +138,6 @@ __global__ void pack_kernel(RawScene raw, int N, int P, int L, float4* geom, flo
   }
 }
 
-// Scene centre C (middle of the sphere centres' bounding box), largest radius
-// and largest |c - C|, for the mirror-ray prefilter.  One workgroup.
-__global__ __launch_bounds__(256) void bounds_kernel(const float4* __restrict__ geom,
-                                                     const float2* __restrict__ rad, int N,
-                                                     float4* __restrict__ consts) {
-  __shared__ float red[7][256];
-  const int t = threadIdx.x;
-  float lo[3] = {3.0e38f, 3.0e38f, 3.0e38f}, hi[3] = {-3.0e38f, -3.0e38f, -3.0e38f}, rmax = 0.f;
-  for (int i = t; i < N; i += 256) {
-    float4 g = geom[i];
-    lo[0] = fminf(lo[0], g.x); lo[1] = fminf(lo[1], g.y); lo[2] = fminf(lo[2], g.z);
-    hi[0] = fmaxf(hi[0], g.x); hi[1] = fmaxf(hi[1], g.y); hi[2] = fmaxf(hi[2], g.z);
-    rmax = fmaxf(rmax, rad[i].x);
-  }
-  for (int k = 0; k < 3; ++k) {
-    red[k][t] = lo[k];
-    red[3 + k][t] = hi[k];
-  }
-  red[6][t] = rmax;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (t < w) {
-      for (int k = 0; k < 3; ++k) {
-        red[k][t] = fminf(red[k][t], red[k][t + w]);
-        red[3 + k][t] = fmaxf(red[3 + k][t], red[3 + k][t + w]);
-      }
-      red[6][t] = fmaxf(red[6][t], red[6][t + w]);
-    }
-    __syncthreads();
-  }
-  float C[3];
-  for (int k = 0; k < 3; ++k) C[k] = N > 0 ? 0.5f * (red[k][0] + red[3 + k][0]) : 0.0f;
-  const float rm = red[6][0];
-  __syncthreads();
-  float cm = 0.0f;
-  for (int i = t; i < N; i += 256) {
-    float4 g = geom[i];
-    double dx = (double)g.x - C[0], dy = (double)g.y - C[1], dz = (double)g.z - C[2];
-    cm = fmaxf(cm, (float)sqrt(dx * dx + dy * dy + dz * dz) * 1.0001f);
-  }
-  red[0][t] = cm;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (t < w) red[0][t] = fmaxf(red[0][t], red[0][t + w]);
-    __syncthreads();
-  }
-  if (t == 0) {
-    consts[0] = make_float4(C[0], C[1], C[2], rm);
-    consts[1] = make_float4(red[0][0], 0.0f, 0.0f, 0.0f);
-  }
-}
-
-// Mirror-ray prefilter table: (c' = c - C, K = |c'|^2 - r^2 - G |c'|^2 - 12 u r^2),
-// built in double from the rounded c'; padding entries can never pass.
-__global__ void refl_kernel(const float4* __restrict__ geom, const float2* __restrict__ rad,
-                            int N, const float4* __restrict__ consts, float4* __restrict__ refl) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const float4 k0 = consts[0];
-  if (i < N) {
-    float4 g = geom[i];
-    float cx = (float)((double)g.x - k0.x), cy = (float)((double)g.y - k0.y),
-          cz = (float)((double)g.z - k0.z);
-    double r = rad[i].x;
-    double cc = (double)cx * cx + (double)cy * cy + (double)cz * cz;
-    double K = cc - r * r - (double)kReflGamma * cc - 12.0 * 5.9604644775390625e-08 * r * r;
-    refl[i] = make_float4(cx, cy, cz, (float)K);
-  } else if (i < pad_spheres(N) + kGroup) {
-    refl[i] = make_float4(0.0f, 0.0f, 0.0f, 1.0e30f);
-  }
-}
-
 hipError_t launch_pack(const rt_scene_s& sc, const RawScene& raw, hipStream_t stream) {
   int n = pad_spheres(sc.n_spheres) + kGroup;
   if (sc.n_planes > n) n = sc.n_planes;
@@ -216,16 +145,6 @@ hipError_t launch_pack(const rt_scene_s& sc, const RawScene& raw, hipStream_t st
   hipLaunchKernelGGL(pack_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, raw,
                      sc.n_spheres, sc.n_planes, sc.n_lights, sc.geom, sc.rad, sc.mat, sc.shine,
                      sc.pgeom, sc.light, sc.light_cone);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(bounds_kernel, dim3(1), dim3(256), 0, stream, (const float4*)sc.geom,
-                     (const float2*)sc.rad, sc.n_spheres, sc.consts);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const int nr = pad_spheres(sc.n_spheres) + kGroup;
-  hipLaunchKernelGGL(refl_kernel, dim3((nr + 255) / 256), dim3(256), 0, stream,
-                     (const float4*)sc.geom, (const float2*)sc.rad, sc.n_spheres,
-                     (const float4*)sc.consts, sc.refl);
   return hipGetLastError();
 }
 

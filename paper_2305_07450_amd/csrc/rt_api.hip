@@ -237,8 +237,6 @@ rt_status rt_scene_upload(const rt_scene_desc* d, void* stream, rt_scene* out) {
   size_t o_light = take(L * sizeof(float4));
   size_t o_eye_cone = take((N4 + kGroup) * sizeof(float4));
   size_t o_light_cone = take((L * N4 + kGroup) * sizeof(float4));
-  size_t o_refl = take((N4 + kGroup) * sizeof(float4));
-  size_t o_consts = take(2 * sizeof(float4));
   sc->staging_floats = 9 * N + 9 * P + 4 * L;
   size_t o_stage = take(sc->staging_floats * sizeof(float));
   size_t o_part = take((size_t)blocks * sc->grad_stride * sizeof(float));
@@ -258,8 +256,6 @@ rt_status rt_scene_upload(const rt_scene_desc* d, void* stream, rt_scene* out) {
   sc->light = (float4*)(base + o_light);
   sc->eye_cone = (float4*)(base + o_eye_cone);
   sc->light_cone = (float4*)(base + o_light_cone);
-  sc->refl = (float4*)(base + o_refl);
-  sc->consts = (float4*)(base + o_consts);
   sc->staging = (float*)(base + o_stage);
   sc->partials = (float*)(base + o_part);
   st = upload_values(sc, d, (hipStream_t)stream);

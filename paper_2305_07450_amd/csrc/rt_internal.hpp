@@ -27,8 +27,6 @@ struct rt_scene_s {
   float4* light = nullptr; // [L]
   float4* eye_cone = nullptr;    // [n4+kGroup] rebuilt for the camera of each call
   float4* light_cone = nullptr;  // [L*n4 + kGroup]  rows of n4, rebuilt by every upload/update
-  float4* refl = nullptr;        // [n4+kGroup] mirror-ray prefilter table
-  float4* consts = nullptr;      // [2] scene centre, max radius, max centre distance
   float* staging = nullptr;     // raw copy of host desc arrays
   size_t staging_floats = 0;
   float* partials = nullptr;    // adjoint partials [kAdjointBlocks][grad_stride]
@@ -38,7 +36,6 @@ struct rt_scene_s {
     rtk::SceneDev s;
     s.geom = geom; s.rad = rad; s.mat = mat; s.shine = shine; s.pgeom = pgeom; s.light = light;
     s.eye_cone = eye_cone; s.light_cone = light_cone;
-    s.refl = refl; s.consts = consts;
     s.n4 = rtk::pad_spheres(n_spheres);
     s.n_spheres = n_spheres; s.n_planes = n_planes; s.n_lights = n_lights;
     s.spec_model = spec_model;

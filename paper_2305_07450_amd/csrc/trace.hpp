@@ -37,8 +37,6 @@ struct SceneDev {
   const float4* light;   // [L]   position, intensity
   const float4* eye_cone;    // [N]    cone of each sphere seen from the eye
   const float4* light_cone;  // [L][N] cone of each sphere seen from each light
-  const float4* refl;        // [N]    (c - C, K) for the mirror-ray prefilter
-  const float4* consts;      // [2]    (C, max r), (max |c - C|, 0, 0, 0)
   int n_spheres, n_planes, n_lights, spec_model;
   int n4;   // sphere tables padded to a multiple of kGroup (+kGroup for prefetch)
   float ambient, spec_strength, t_min;
@@ -54,19 +52,6 @@ constexpr float kPadConeW = 2.0f;
 constexpr float kPadR2 = -1.0f;
 
 __host__ __device__ constexpr int pad_spheres(int n) { return (n + kGroup - 1) / kGroup * kGroup; }
-
-// Mirror rays start anywhere, so they get a cheaper conservative test in the
-// classic form Delta = b^2 - |oc|^2 + r^2 evaluated about the scene centre C
-// (c' = c - C, o' = o - C, b = (c' - o').d):
-//   e = b^2 - (K - 2 c'.o'),   K = |c'|^2 - r^2 - G |c'|^2,
-// and the sphere is a candidate iff e >= (1 - G) |o'|^2, i.e. Delta >= -M
-// with M = G (|c'|^2 + |o'|^2), and b >= -(max r) - slack (not wholly behind
-// the origin).  That form cancels, but its FP32 error is at most about
-// 26 u (|c'|^2 + |o'|^2) (u = 2^-24); G = 128 u keeps M well above it (an
-// FP32 emulation over 12M random near-tangent pairs used under 10% of M).
-// Candidates run the exact test, so the image is the exact test's.
-constexpr float kReflGamma = 128.0f * 5.9604644775390625e-08f;
-constexpr float kReflSlack = 16.0f * 5.9604644775390625e-08f;
 
 // Cone of a sphere seen from a point q (the eye, or a light): unit axis a
 // towards the centre and a threshold w such that every unit direction u with
@@ -276,29 +261,6 @@ __device__ __forceinline__ void closest_hit(const SceneDev& s, const Ray& r, flo
       c0 = n0;
       c1 = n1;
     }
-  } else if (kPrefilter) {
-    const float4 k0 = ld4(s.consts, 0), k1 = ld4(s.consts, 1);
-    const float opx = r.ox - k0.x, opy = r.oy - k0.y, opz = r.oz - k0.z;
-    const float od = dot3(opx, opy, opz, r.dx, r.dy, r.dz);
-    const float m2x = -2.0f * opx, m2y = -2.0f * opy, m2z = -2.0f * opz;
-    const float oo = dot3(opx, opy, opz, opx, opy, opz);
-    const float thr_e = oo * (1.0f - kReflGamma);
-    const float thr_b = -(k0.w + kReflSlack * (k1.x + fmaxf(1.0f, oo)));
-    rt_v16 c0 = ld16(s.refl, 0), c1 = ld16(s.refl, 4);
-    for (int i = 0; i < s.n4; i += kGroup) {
-      rt_v16 n0 = ld16(s.refl, i + 8), n1 = ld16(s.refl, i + 12);
-#pragma unroll
-      for (int k = 0; k < kGroup; ++k) {
-        float4 a = part(k < 4 ? c0 : c1, k & 3);
-        float bb = fmaf(a.x, r.dx, fmaf(a.y, r.dy, fmaf(a.z, r.dz, -od)));
-        float q = fmaf(a.x, m2x, fmaf(a.y, m2y, fmaf(a.z, m2z, a.w)));
-        float e = fmaf(bb, bb, -q);
-        if (wave_any(e >= thr_e && bb >= thr_b))
-          test_sphere(ld4(s.geom, i + k), i + k, r, tmin, t_best, id_best);
-      }
-      c0 = n0;
-      c1 = n1;
-    }
   } else {
     rt_v16 c0 = ld16(s.geom, 0), c1 = ld16(s.geom, 4);
     for (int i = 0; i < s.n4; i += kGroup) {
@@ -484,52 +446,81 @@ struct NoRecords {
   __device__ __forceinline__ void lit(int, uint32_t) {}
 };
 
-// The whole path of one pixel.  `sink.seg(k, id)` and `sink.lit(k, mask)` see
-// every traced segment; the caller marks untraced segments.  Returns the
-// number of segments traced.
+// State of a path between segments: the ray, its throughput, the colour so
+// far and the plane the ray leaves (-1 if none).
+struct PathState {
+  Ray r;
+  float T;
+  float cr, cg, cb;
+  int from_plane;
+};
+
+// Segment k of a path: closest hit, light terms with shadow rays, colour
+// contribution T_k (A_k w_k a_k + S_k) (or T_k bg on a miss), then the mirror
+// ray when k < depth.  Returns the id hit; the path continues iff the id is
+// >= 0 and k < depth.  `sink.seg(k, id)` / `sink.lit(k, mask)` see the
+// segment.  Every kernel runs a segment through this one function.
+template <bool kFromEye, bool kPrefilter, class Sink, class Cnt>
+__device__ __forceinline__ int trace_segment(const SceneDev& s, PathState& ps, int k, int depth,
+                                             Sink& sink, Cnt& cnt) {
+  float t;
+  int id;
+  if (kFromEye)
+    closest_hit<true, kPrefilter>(s, ps.r, t, id);
+  else
+    closest_hit<false, kPrefilter>(s, ps.r, t, id, ps.from_plane);
+  cnt.ray(k == 0 ? kCntPrimary : kCntReflection);
+  cnt.tests(s.n_spheres, s.n_planes);
+  sink.seg(k, id);
+  if (id < 0) {
+    ps.cr = fmaf(ps.T, s.bg_r, ps.cr);
+    ps.cg = fmaf(ps.T, s.bg_g, ps.cg);
+    ps.cb = fmaf(ps.T, s.bg_b, ps.cb);
+    return id;
+  }
+  Surface f = surface_at(s, ps.r, t, id);
+  float A, S;
+  sink.lit(k, light_terms<kPrefilter>(s, f, ps.r, A, S, cnt));
+  if (k < depth) {
+    float w = A * (1.0f - f.kr);
+    ps.cr = fmaf(ps.T, fmaf(w, f.ar, S), ps.cr);
+    ps.cg = fmaf(ps.T, fmaf(w, f.ag, S), ps.cg);
+    ps.cb = fmaf(ps.T, fmaf(w, f.ab, S), ps.cb);
+    ps.T = ps.T * (A * f.kr);
+    reflect_ray(ps.r, f);
+    ps.from_plane = id >= s.n_spheres ? id : -1;
+  } else {
+    ps.cr = fmaf(ps.T, fmaf(A, f.ar, S), ps.cr);
+    ps.cg = fmaf(ps.T, fmaf(A, f.ag, S), ps.cg);
+    ps.cb = fmaf(ps.T, fmaf(A, f.ab, S), ps.cb);
+  }
+  return id;
+}
+
+// The whole path of one pixel in one lane.  `sink.seg(k, id)` and
+// `sink.lit(k, mask)` see every traced segment; the caller marks untraced
+// segments.  Returns the number of segments traced.
 template <class Sink, class Cnt = NoCount, bool kPrefilter = true>
 __device__ __forceinline__ int trace_path(const SceneDev& s, Ray r, int depth, float& cr,
                                           float& cg, float& cb, int& prim, Sink& sink,
                                           Cnt&& cnt = Cnt()) {
-  float T = 1.0f;
-  cr = 0.0f; cg = 0.0f; cb = 0.0f;
-  prim = kMiss;
-  int k = 0;
-  int from_plane = -1;
-  for (; k <= depth; ++k) {
-    float t;
-    int id;
-    if (k == 0)
-      closest_hit<true, kPrefilter>(s, r, t, id);
-    else
-      closest_hit<false, kPrefilter>(s, r, t, id, from_plane);
-    cnt.ray(k == 0 ? kCntPrimary : kCntReflection);
-    cnt.tests(s.n_spheres, s.n_planes);
-    if (k == 0) prim = id;
-    sink.seg(k, id);
-    if (id < 0) {
-      cr = fmaf(T, s.bg_r, cr);
-      cg = fmaf(T, s.bg_g, cg);
-      cb = fmaf(T, s.bg_b, cb);
-      return k + 1;
-    }
-    Surface f = surface_at(s, r, t, id);
-    float A, S;
-    sink.lit(k, light_terms<kPrefilter>(s, f, r, A, S, cnt));
-    if (k < depth) {
-      float w = A * (1.0f - f.kr);
-      cr = fmaf(T, fmaf(w, f.ar, S), cr);
-      cg = fmaf(T, fmaf(w, f.ag, S), cg);
-      cb = fmaf(T, fmaf(w, f.ab, S), cb);
-      T = T * (A * f.kr);
-      reflect_ray(r, f);
-      from_plane = id >= s.n_spheres ? id : -1;
-    } else {
-      cr = fmaf(T, fmaf(A, f.ar, S), cr);
-      cg = fmaf(T, fmaf(A, f.ag, S), cg);
-      cb = fmaf(T, fmaf(A, f.ab, S), cb);
+  PathState ps;
+  ps.r = r;
+  ps.T = 1.0f;
+  ps.cr = 0.0f; ps.cg = 0.0f; ps.cb = 0.0f;
+  ps.from_plane = -1;
+  prim = trace_segment<true, kPrefilter>(s, ps, 0, depth, sink, cnt);
+  int k = 1;
+  if (prim >= 0 && depth > 0) {
+    for (; k <= depth; ++k) {
+      const int id = trace_segment<false, kPrefilter>(s, ps, k, depth, sink, cnt);
+      if (id < 0 || k == depth) {
+        ++k;
+        break;
+      }
     }
   }
+  cr = ps.cr; cg = ps.cg; cb = ps.cb;
   return k;
 }
 

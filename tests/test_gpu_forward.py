@@ -127,24 +127,28 @@ def test_work_counters_match_oracle(rt, oracle_mod, config):
         assert abs(got[k] - want[k]) <= 1e-3 * max(want[k], 1), (k, got[k], want[k])
 
 
+ALL_FLAGS = (0, 1)   # with and without the cone prefilters
+
+
 @pytest.mark.parametrize("config", [0, 1, 2, 4])
 def test_prefilters_change_no_bits(rt, config):
-    """The cheap tests that let a ray skip a sphere (cones from the eye and the
-    lights, the mirror-ray bound) only skip pairs the exact test rejects: the
-    image, ids and records are the same bits with them switched off."""
+    """The cone tests that let a ray skip a sphere (cones seen from the eye
+    and from the lights) only skip pairs the exact test rejects: image, ids
+    and records are the same bits with them switched off."""
     wl = scenegen.make_workload(config)
     W, H, D = wl.W, wl.H, wl.depth
     with rt.SceneHandle(wl.scene) as h:
         out = []
-        for flags in (0, rt.RT_RENDER_NO_PREFILTER):
+        for flags in ALL_FLAGS:
             rgb = torch.empty((H, W, 3), device="cuda")
             ids = torch.empty((H, W), dtype=torch.int32, device="cuda")
             rec = rt.Records(W, H, D)
             rt.rt_render_ex(h.handle, wl.camera, W, H, D, rgb, ids, rec, flags)
             torch.cuda.synchronize()
             out.append((rgb.cpu(), ids.cpu(), rec.buf.cpu()))
-    for a, b in zip(out[0], out[1]):
-        assert torch.equal(a, b)
+    for other in out[1:]:
+        for a, b in zip(out[0], other):
+            assert torch.equal(a, b)
 
 
 @pytest.mark.parametrize("seed", range(6))
@@ -154,9 +158,10 @@ def test_prefilters_change_no_bits_small_scenes(rt, seed):
     W, H, D = 123, 77, 5
     with rt.SceneHandle(s) as h:
         imgs = []
-        for flags in (0, rt.RT_RENDER_NO_PREFILTER):
+        for flags in ALL_FLAGS:
             rgb = torch.empty((H, W, 3), device="cuda")
             rt.rt_render_ex(h.handle, cam, W, H, D, rgb, None, None, flags)
             torch.cuda.synchronize()
             imgs.append(rgb.cpu())
-    assert torch.equal(imgs[0], imgs[1])
+    for im in imgs[1:]:
+        assert torch.equal(imgs[0], im)
