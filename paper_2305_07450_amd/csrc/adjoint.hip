@@ -123,6 +123,17 @@ __global__ __launch_bounds__(256) void adjoint_kernel(SceneDev s, CameraDev c, i
       int K = 0;          // segments with a hit
       bool ends_in_miss = false;
       float gr = 0.f, gg = 0.f, gb = 0.f;
+      if (!kHasRecords) {
+        // re-trace with the forward kernel's code; lanes outside the image
+        // run along (the path code needs the whole wave), without a path
+        for (int k = 0; k <= depth; ++k) rr.ids[k] = kNotTraced;
+        if (wave_any(valid)) {
+          float cr, cg, cb;
+          int prim;
+          trace_path(s, primary_ray(c, valid ? x : c.W - 1, valid ? y : c.H - 1), depth, valid,
+                     cr, cg, cb, prim, rr);
+        }
+      }
       if (valid) {
         gr = grad_rgb[3 * pix + 0];
         gg = grad_rgb[3 * pix + 1];
@@ -132,11 +143,6 @@ __global__ __launch_bounds__(256) void adjoint_kernel(SceneDev s, CameraDev c, i
             rr.ids[k] = rec_ids[k * plane + pix];
             rr.lits[k] = rec_lit[k * plane + pix];
           }
-        } else {
-          for (int k = 0; k <= depth; ++k) rr.ids[k] = kNotTraced;
-          float cr, cg, cb;
-          int prim;
-          trace_path(s, primary_ray(c, x, y), depth, cr, cg, cb, prim, rr);
         }
         const int n_prims = s.n_spheres + s.n_planes;
         for (int k = 0; k <= depth; ++k) {

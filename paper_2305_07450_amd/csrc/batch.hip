@@ -90,15 +90,20 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchJob* __restrict__
     const int tx = tile % job.tiles_x, ty = tile / job.tiles_x;
     const int x = tx * tile_w + (lane % wave_w);
     const int y = ty * tile_h + wave * wave_h + (lane / wave_w);
-    if (x < job.c.W && y < job.c.H) {
+    // lanes outside the image run along without output (see render_kernel)
+    const bool live = x < job.c.W && y < job.c.H;
+    if (wave_any(live)) {
       float cr, cg, cb;
       int prim;
       NoRecords sink;
-      trace_path(job.s, primary_ray(job.c, x, y), job.depth, cr, cg, cb, prim, sink);
-      const int64_t pix = (int64_t)y * job.c.W + x;
-      job.rgb[3 * pix + 0] = cr;
-      job.rgb[3 * pix + 1] = cg;
-      job.rgb[3 * pix + 2] = cb;
+      trace_path(job.s, primary_ray(job.c, live ? x : job.c.W - 1, live ? y : job.c.H - 1),
+                 job.depth, live, cr, cg, cb, prim, sink);
+      if (live) {
+        const int64_t pix = (int64_t)y * job.c.W + x;
+        job.rgb[3 * pix + 0] = cr;
+        job.rgb[3 * pix + 1] = cg;
+        job.rgb[3 * pix + 2] = cb;
+      }
     }
   }
 }

@@ -37,26 +37,33 @@ __global__ __launch_bounds__(256) void render_kernel(SceneDev s, CameraDev c, in
   const int wave = threadIdx.x >> 6;
   const int x = blockIdx.x * kBlock + (wave & 1) * kTile + (lane & 7);
   const int y = blockIdx.y * kBlock + (wave >> 1) * kTile + (lane >> 3);
-  if (x >= c.W || y >= c.H) return;
-  const int64_t pix = (int64_t)y * c.W + x;
-  Ray r = primary_ray(c, x, y);
+  // lanes outside the image run along (clamped pixel, no output) so that the
+  // whole wave executes the path code together; a wave with no pixel leaves
+  const bool live = x < c.W && y < c.H;
+  if (!wave_any(live)) return;
+  const int64_t pix = live ? (int64_t)y * c.W + x : 0;
+  Ray r = primary_ray(c, live ? x : c.W - 1, live ? y : c.H - 1);
   float cr, cg, cb;
   int prim;
   if (kRecords) {
     RecordSink sink{rec_ids, rec_lit, (int64_t)c.W * c.H, pix};
-    int traced = trace_path<RecordSink, NoCount, kPrefilter>(s, r, depth, cr, cg, cb, prim, sink);
-    for (int k = traced; k <= depth; ++k) {
-      rec_ids[k * sink.plane + pix] = kNotTraced;
-      rec_lit[k * sink.plane + pix] = 0;
+    int traced = trace_path<RecordSink, NoCount, kPrefilter>(s, r, depth, live, cr, cg, cb, prim, sink);
+    if (live) {
+      for (int k = traced; k <= depth; ++k) {
+        rec_ids[k * sink.plane + pix] = kNotTraced;
+        rec_lit[k * sink.plane + pix] = 0;
+      }
     }
   } else {
     NoRecords sink;
-    trace_path<NoRecords, NoCount, kPrefilter>(s, r, depth, cr, cg, cb, prim, sink);
+    trace_path<NoRecords, NoCount, kPrefilter>(s, r, depth, live, cr, cg, cb, prim, sink);
   }
-  rgb[3 * pix + 0] = cr;
-  rgb[3 * pix + 1] = cg;
-  rgb[3 * pix + 2] = cb;
-  if (id_out) id_out[pix] = prim;
+  if (live) {
+    rgb[3 * pix + 0] = cr;
+    rgb[3 * pix + 1] = cg;
+    rgb[3 * pix + 2] = cb;
+    if (id_out) id_out[pix] = prim;
+  }
 }
 
 // Counting launch: the same paths, plus the algorithmic counters summed per
@@ -68,11 +75,13 @@ __global__ __launch_bounds__(256) void count_kernel(SceneDev s, CameraDev c, int
   const int x = blockIdx.x * kBlock + (wave & 1) * kTile + (lane & 7);
   const int y = blockIdx.y * kBlock + (wave >> 1) * kTile + (lane >> 3);
   Count cnt;
-  if (x < c.W && y < c.H) {
+  const bool live = x < c.W && y < c.H;
+  if (wave_any(live)) {
     float cr, cg, cb;
     int prim;
     NoRecords sink;
-    trace_path(s, primary_ray(c, x, y), depth, cr, cg, cb, prim, sink, cnt);
+    trace_path(s, primary_ray(c, live ? x : c.W - 1, live ? y : c.H - 1), depth, live, cr, cg,
+               cb, prim, sink, cnt);
   }
   for (int j = 0; j < kNumCounts; ++j) {
     int v = cnt.c[j];

@@ -201,20 +201,38 @@ struct Count {
   __device__ __forceinline__ void ray(int kind) { c[kind] += 1; }
 };
 
-// Closest hit over every primitive: smallest root, ties to the lower id
-// (strict < while scanning ids in ascending order).  `from_plane` is the
-// plane a mirror ray leaves (-1 otherwise): a ray reflected off a plane moves
-// away from it and never meets it again, so that plane is not tested; this
-// keeps FP32 rounding of the start point from re-hitting it at grazing angles.
-//
-// Primary rays (kFromEye) all start at the eye, so each sphere is first
-// tested against its cone seen from the eye (3 FMA-class ops and a compare);
-// only directions inside the cone run the exact test.  The exact test is the
-// same code in both paths, so both give the same bits.
-// True when any active lane of the wave passes: a branch on it is taken or
-// skipped by the whole wave, so no exec mask is saved or restored, and the
-// per-lane effect inside is applied with selects.
+// ---- Wave-level helpers ---------------------------------------------------
+// Branches on wave_any() are taken or skipped by the whole wave, so no exec
+// mask is saved or restored, and the per-lane effect inside is applied with
+// selects.  The path code below keeps every lane of a wave executing (lanes
+// without work carry a `live` flag instead of branching away), which the
+// cross-lane reductions of the wave bounds rely on; wave_full() checks it and
+// a bound is only used when it holds.
 __device__ __forceinline__ bool wave_any(bool p) { return __builtin_amdgcn_ballot_w64(p) != 0; }
+__device__ __forceinline__ uint64_t wave_mask(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+__device__ __forceinline__ bool wave_full() { return __builtin_amdgcn_read_exec() == ~0ull; }
+
+__device__ __forceinline__ float lane_read(float v, int lane) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+}
+__device__ __forceinline__ float4 lane_read4(float4 v, int lane) {
+  return make_float4(lane_read(v.x, lane), lane_read(v.y, lane), lane_read(v.z, lane),
+                     lane_read(v.w, lane));
+}
+template <int kCtrl>
+__device__ __forceinline__ float dpp(float v) {
+  return __builtin_bit_cast(float,
+                            __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), kCtrl, 0xf, 0xf, true));
+}
+// Minimum over all 64 lanes (all executing), in every lane: quad swaps, half-row
+// and row mirrors within each row of 16, then the four row results.
+__device__ __forceinline__ float wave_min(float v) {
+  v = fminf(v, dpp<0xB1>(v));    // quad_perm [1, 0, 3, 2]
+  v = fminf(v, dpp<0x4E>(v));    // quad_perm [2, 3, 0, 1]
+  v = fminf(v, dpp<0x141>(v));   // row_half_mirror
+  v = fminf(v, dpp<0x140>(v));   // row_mirror
+  return fminf(fminf(lane_read(v, 0), lane_read(v, 16)), fminf(lane_read(v, 32), lane_read(v, 48)));
+}
 
 // Exact test of sphere i (geometry g) against the ray; keeps the nearest.
 __device__ __forceinline__ void test_sphere(float4 g, int i, const Ray& r, float tmin,
@@ -240,36 +258,211 @@ __device__ __forceinline__ float cone_excess(float4 a, float ux, float uy, float
   return fmaf(a.x, ux, fmaf(a.y, uy, fmaf(a.z, uz, -a.w)));
 }
 
+// ---- Wave cones: one bound for the directions of a whole wave -------------
+// The rays of a wave that share an origin (primary rays from the eye, shadow
+// rays reversed from one light) point in nearly the same direction.  A cone
+// (axis e, half-angle phi) holding every participating direction u lets one
+// lane per sphere decide, for 64 spheres at once, whether any lane can pass
+// that sphere's own cone test; the other spheres are skipped for the wave.
+//
+// Axis: the direction of the first participating lane.  cos(phi): the least
+// e.u over the participating lanes, lowered by 2e-6, which covers the FP32
+// error of the 3-term dot products of near-unit vectors, so the true angle
+// between e and every u is at most phi.
+struct WaveCone {
+  float ex, ey, ez;
+  float c, s;   // cos(phi), sin(phi)
+  bool on;      // usable: all lanes executing, some participate, phi small enough
+};
+
+// Widest wave cone still worth its cost (cos of the half-angle).
+constexpr float kWaveConeMinCos = 0.5f;
+
+__device__ __forceinline__ WaveCone wave_cone(bool take, float ux, float uy, float uz) {
+  WaveCone w;
+  const uint64_t m = wave_mask(take);
+  w.on = m != 0 && wave_full();
+  w.ex = w.ey = w.ez = 0.0f;
+  w.c = -1.0f;
+  w.s = 0.0f;
+  if (w.on) {
+    const int f = (int)__builtin_ctzll(m);
+    w.ex = lane_read(ux, f);
+    w.ey = lane_read(uy, f);
+    w.ez = lane_read(uz, f);
+    const float c = wave_min(take ? dot3(w.ex, w.ey, w.ez, ux, uy, uz) : 2.0f) - 2e-6f;
+    w.c = c;
+    w.s = fsqrt(fmaxf(fmaf(-c, c, 1.0f), 0.0f));
+    w.on = c > kWaveConeMinCos;
+  }
+  return w;
+}
+
+// Whether some direction of the wave cone can pass the cone test of sphere
+// cone (a, w) (a.u - w >= 0 in FP32).  A passing u has angle(a, u) <= alpha
+// with cos(alpha) = w - 4e-6 (the FP32 error of that test and of |a|, |u|
+// differing from 1), and angle(e, u) <= phi, so angle(a, e) <= alpha + phi:
+// either alpha + phi >= pi (cos(alpha) <= -cos(phi)), or
+// a.e >= cos(alpha + phi) = cos(alpha) cos(phi) - sin(alpha) sin(phi).  The
+// 1e-5 slack is several times the rounding of this test itself.  Cones with
+// w = -2 (every direction a candidate) always pass.
+__device__ __forceinline__ bool cone_may_pass(const WaveCone& wc, float4 a) {
+  const float ca = a.w - 4e-6f;
+  const float sa = fsqrt(fmaxf(fmaf(-ca, ca, 1.0f), 0.0f));
+  const float thr = fmaf(ca, wc.c, -(sa * wc.s));
+  return (ca + wc.c <= 1e-6f) | (dot3(a.x, a.y, a.z, wc.ex, wc.ey, wc.ez) >= thr - 1e-5f);
+}
+
+// ---- Wave bundles: one bound for mirror rays with different origins --------
+// Origins in a ball (centre m = the first participating lane's origin, radius
+// rho = the largest distance to it, raised by 1e-5 relative for rounding) and
+// directions in a wave cone (e, phi), with phi < 90 degrees.  Every point
+// o + t d with t >= 0 then lies in the cone with apex v = m - e rho / sin(phi),
+// axis e and half-angle phi: that cone holds the ball (the ball's distance to
+// its side is rho) and, being convex, every step from a point of it along a
+// direction within phi of its axis.  A tiny phi is widened to asin(1e-3) so
+// that the apex stays near.
+struct WaveBundle {
+  float vx, vy, vz;   // apex
+  float ex, ey, ez;   // axis
+  float c, s;         // cos(phi), sin(phi)
+  float reach;        // rho / sin(phi) + rho: farthest origin from the apex
+  bool on;
+};
+
+// Widest bundle still worth its cost (cos of the half-angle).
+constexpr float kBundleMinCos = 0.5f;
+
+__device__ __forceinline__ WaveBundle wave_bundle(bool take, const Ray& r) {
+  WaveBundle b;
+  const uint64_t m = wave_mask(take);
+  b.on = m != 0 && wave_full();
+  b.vx = b.vy = b.vz = b.ex = b.ey = b.ez = 0.0f;
+  b.c = -1.0f;
+  b.s = 0.0f;
+  b.reach = 0.0f;
+  if (b.on) {
+    const int f = (int)__builtin_ctzll(m);
+    const float mx = lane_read(r.ox, f), my = lane_read(r.oy, f), mz = lane_read(r.oz, f);
+    b.ex = lane_read(r.dx, f);
+    b.ey = lane_read(r.dy, f);
+    b.ez = lane_read(r.dz, f);
+    const float qx = r.ox - mx, qy = r.oy - my, qz = r.oz - mz;
+    const float rho2 = wave_min(take ? -dot3(qx, qy, qz, qx, qy, qz) : 0.0f);
+    const float rho = fmaf(fsqrt(-rho2), 1.00001f, 1e-6f);
+    float c = wave_min(take ? dot3(b.ex, b.ey, b.ez, r.dx, r.dy, r.dz) : 2.0f) - 2e-6f;
+    // decided on phi itself: sin(phi) is also small when phi is near 180 degrees
+    b.on = c > kBundleMinCos;
+    float sn = fsqrt(fmaxf(fmaf(-c, c, 1.0f), 0.0f));
+    if (sn < 1e-3f) {   // phi near 0 (c > kBundleMinCos > 0 here)
+      sn = 1e-3f;
+      c = 0.9999995f;   // below sqrt(1 - 1e-6)
+    }
+    b.c = c;
+    b.s = sn;
+    const float back = rho / sn;
+    b.vx = fmaf(-b.ex, back, mx);
+    b.vy = fmaf(-b.ey, back, my);
+    b.vz = fmaf(-b.ez, back, mz);
+    b.reach = back + rho;
+  }
+  return b;
+}
+
+// Whether some ray of the bundle can meet sphere (centre g.xyz, radius rad)
+// in the exact test: whether the sphere, grown by 1e-4 r + 2e-5 (D + reach)
+// + 1e-5 (D = distance to the apex; many times the FP32 error of the exact
+// test and of this one), meets the bundle's cone: it holds the apex, or the
+// angle between its centre and the axis is at most phi + asin(r'/D).
+__device__ __forceinline__ bool sphere_may_meet(const WaveBundle& b, float4 g, float rad) {
+  const float wx = g.x - b.vx, wy = g.y - b.vy, wz = g.z - b.vz;
+  const float inv = frsq(dot3(wx, wy, wz, wx, wy, wz));
+  const float D = dot3(wx, wy, wz, wx, wy, wz) * inv;
+  const float rg = fmaf(rad, 1.0001f, fmaf(2e-5f, D + b.reach, 1e-5f));
+  const float sb = rg * inv;
+  const float cb = fsqrt(fmaxf(fmaf(-sb, sb, 1.0f), 0.0f));
+  const float ca = dot3(wx, wy, wz, b.ex, b.ey, b.ez) * inv;
+  const float thr = fmaf(b.c, cb, -(b.s * sb));
+  return (sb >= 1.0f) | (b.c + cb <= 1e-6f) | (ca >= thr - 1e-5f);
+}
+
+// Closest hit over every primitive: smallest root, ties to the lower id
+// (strict < while scanning ids in ascending order).  `from_plane` is the
+// plane a mirror ray leaves (-1 otherwise): a ray reflected off a plane moves
+// away from it and never meets it again, so that plane is not tested; this
+// keeps FP32 rounding of the start point from re-hitting it at grazing angles.
+// `live` marks the lanes whose result is used; the others run along.
+//
+// Primary rays (kFromEye) all start at the eye, so each sphere is first
+// tested against its cone seen from the eye (3 FMA-class ops and a compare);
+// only directions inside the cone run the exact test.  With a wave cone, 64
+// spheres at a time are first tested against the whole wave, and only the
+// spheres some lane may see run the per-lane cone test.  Mirror rays are
+// bounded by a wave bundle, and only the spheres it may meet run the exact
+// test.  Skipped spheres are ones the exact test would reject, and the exact
+// test is the same code in every path, so all paths give the same bits.
 template <bool kFromEye = false, bool kPrefilter = true>
-__device__ __forceinline__ void closest_hit(const SceneDev& s, const Ray& r, float& t_best,
-                                            int& id_best, int from_plane = -1) {
+__device__ __forceinline__ void closest_hit(const SceneDev& s, const Ray& r, bool live,
+                                            float& t_best, int& id_best, int from_plane = -1) {
   t_best = __builtin_inff();
   id_best = kMiss;
   const float tmin = s.t_min;
   if (kFromEye && kPrefilter) {
-    // the exact test runs for every lane once any lane is inside the cone, so
-    // the result is the exact test's whatever the cone decides
-    rt_v16 c0 = ld16(s.eye_cone, 0), c1 = ld16(s.eye_cone, 4);
-    for (int i = 0; i < s.n4; i += kGroup) {
-      rt_v16 n0 = ld16(s.eye_cone, i + 8), n1 = ld16(s.eye_cone, i + 12);
-#pragma unroll
-      for (int k = 0; k < kGroup; ++k) {
-        float4 a = part(k < 4 ? c0 : c1, k & 3);
-        if (wave_any(cone_excess(a, r.dx, r.dy, r.dz) >= 0.0f))
-          test_sphere(ld4(s.geom, i + k), i + k, r, tmin, t_best, id_best);
+    const WaveCone wc = wave_cone(live, r.dx, r.dy, r.dz);
+    if (wc.on) {
+      const int lane = __lane_id();
+      for (int base = 0; base < s.n_spheres; base += 64) {
+        const int j = base + lane;
+        const int jc = j < s.n_spheres ? j : s.n_spheres - 1;
+        const float4 a = s.eye_cone[jc];
+        const float4 g = s.geom[jc];
+        uint64_t m = wave_mask((j < s.n_spheres) & cone_may_pass(wc, a));
+        while (m) {
+          const int k = (int)__builtin_ctzll(m);
+          m &= m - 1;
+          if (wave_any(live & (cone_excess(lane_read4(a, k), r.dx, r.dy, r.dz) >= 0.0f)))
+            test_sphere(lane_read4(g, k), base + k, r, tmin, t_best, id_best);
+        }
       }
-      c0 = n0;
-      c1 = n1;
+    } else {
+      rt_v16 c0 = ld16(s.eye_cone, 0), c1 = ld16(s.eye_cone, 4);
+      for (int i = 0; i < s.n4; i += kGroup) {
+        rt_v16 n0 = ld16(s.eye_cone, i + 8), n1 = ld16(s.eye_cone, i + 12);
+#pragma unroll
+        for (int k = 0; k < kGroup; ++k) {
+          float4 a = part(k < 4 ? c0 : c1, k & 3);
+          if (wave_any(live & (cone_excess(a, r.dx, r.dy, r.dz) >= 0.0f)))
+            test_sphere(ld4(s.geom, i + k), i + k, r, tmin, t_best, id_best);
+        }
+        c0 = n0;
+        c1 = n1;
+      }
     }
   } else {
-    rt_v16 c0 = ld16(s.geom, 0), c1 = ld16(s.geom, 4);
-    for (int i = 0; i < s.n4; i += kGroup) {
-      rt_v16 n0 = ld16(s.geom, i + 8), n1 = ld16(s.geom, i + 12);
+    const WaveBundle wb = (!kFromEye && kPrefilter) ? wave_bundle(live, r) : WaveBundle{};
+    if (!kFromEye && kPrefilter && wb.on) {
+      const int lane = __lane_id();
+      for (int base = 0; base < s.n_spheres; base += 64) {
+        const int j = base + lane;
+        const int jc = j < s.n_spheres ? j : s.n_spheres - 1;
+        const float4 g = s.geom[jc];
+        uint64_t m = wave_mask((j < s.n_spheres) & sphere_may_meet(wb, g, s.rad[jc].x));
+        while (m) {
+          const int k = (int)__builtin_ctzll(m);
+          m &= m - 1;
+          test_sphere(lane_read4(g, k), base + k, r, tmin, t_best, id_best);
+        }
+      }
+    } else {
+      rt_v16 c0 = ld16(s.geom, 0), c1 = ld16(s.geom, 4);
+      for (int i = 0; i < s.n4; i += kGroup) {
+        rt_v16 n0 = ld16(s.geom, i + 8), n1 = ld16(s.geom, i + 12);
 #pragma unroll
-      for (int k = 0; k < kGroup; ++k)
-        test_sphere(part(k < 4 ? c0 : c1, k & 3), i + k, r, tmin, t_best, id_best);
-      c0 = n0;
-      c1 = n1;
+        for (int k = 0; k < kGroup; ++k)
+          test_sphere(part(k < 4 ? c0 : c1, k & 3), i + k, r, tmin, t_best, id_best);
+        c0 = n0;
+        c1 = n1;
+      }
     }
   }
   for (int j = 0; j < s.n_planes; ++j) {
@@ -281,14 +474,32 @@ __device__ __forceinline__ void closest_hit(const SceneDev& s, const Ray& r, flo
   }
 }
 
+// Exact occlusion test of sphere i (geometry g) on the reversed shadow ray rr
+// for the lanes not yet occluded; records the first occluder.
+__device__ __forceinline__ void shadow_sphere(float4 g, int i, const Ray& rr, float lim, int self,
+                                              bool& occ, int& first) {
+  float b;
+  float ff = sphere_ff(g, rr, b);
+  const bool in = !occ & (ff <= g.w) & (i != self);
+  if (wave_any(in)) {
+    float sq = fsqrt(in ? g.w - ff : 0.0f);
+    float t0 = -b - sq, t1 = -b + sq;
+    const bool hit = in && ((t0 > 0.0f && t0 < lim) || (t1 > 0.0f && t1 < lim));
+    first = hit ? i : first;
+    occ = occ || hit;
+  }
+}
+
 // Shadow ray between a surface point p and light l at distance `dist`
 // (direction l_dir from p to the light): blocked iff some primitive has a
 // root in (t_min, dist) along the ray from p.  Spheres are tested on the
 // reversed ray from the light, u = -l_dir, where that interval becomes
 // (0, dist - t_min): every shadow ray towards light l shares that origin, so
-// a sphere is first tested against its cone seen from the light and only
+// a sphere is first tested against its cone seen from the light (and, with a
+// wave cone, 64 spheres at a time against the whole wave), and only
 // directions inside the cone run the exact root test.  Each lane stops at its
-// first occluder (ascending id order); the wave stops when all its lanes have.
+// first occluder (ascending id order); the wave stops when all its lanes
+// have.  Lanes with `act` false take no part and report true.
 //
 // `self` is the primitive p lies on.  A shadow ray is only traced when
 // n.l > 0, i.e. it leaves that convex surface outwards and cannot meet it
@@ -296,54 +507,73 @@ __device__ __forceinline__ void closest_hit(const SceneDev& s, const Ray& r, flo
 // skipping it keeps FP32 rounding of p from re-hitting it.
 template <bool kPrefilter, class Cnt>
 __device__ __forceinline__ bool occluded(const SceneDev& s, int l, float4 q, const Surface& f,
-                                         float lx, float ly, float lz, float dist, Cnt& cnt) {
+                                         float lx, float ly, float lz, float dist, bool act,
+                                         Cnt& cnt) {
   const float lim = dist - s.t_min;
   const float ux = -lx, uy = -ly, uz = -lz;
   const float4* cones = s.light_cone + (int64_t)l * s.n4;
   const int self = f.id;
-  bool occ = false;
+  bool occ = !act;
   int first = 0;   // first occluding sphere, for the work counters
   Ray rr;
   rr.ox = q.x; rr.oy = q.y; rr.oz = q.z;
   rr.dx = ux; rr.dy = uy; rr.dz = uz;
-  rt_v16 c0 = ld16(cones, 0), c1 = ld16(cones, 4);
-  for (int i = 0; i < s.n4; i += kGroup) {
-    rt_v16 n0 = ld16(cones, i + 8), n1 = ld16(cones, i + 12);
-#pragma unroll
-    for (int k = 0; k < kGroup; ++k) {
-      float4 a = part(k < 4 ? c0 : c1, k & 3);
-      if (!kPrefilter || wave_any(!occ && cone_excess(a, ux, uy, uz) >= 0.0f)) {
-        float4 g = ld4(s.geom, i + k);
-        float b;
-        float ff = sphere_ff(g, rr, b);
-        const bool in = !occ && ff <= g.w && i + k != self;
-        if (wave_any(in)) {
-          float sq = fsqrt(in ? g.w - ff : 0.0f);
-          float t0 = -b - sq, t1 = -b + sq;
-          const bool hit = in && ((t0 > 0.0f && t0 < lim) || (t1 > 0.0f && t1 < lim));
-          first = hit ? i + k : first;
-          occ = occ || hit;
+  const WaveCone wc = kPrefilter ? wave_cone(act, ux, uy, uz) : WaveCone{};
+  if (kPrefilter && wc.on) {
+    const int lane = __lane_id();
+    bool done = false;
+    for (int base = 0; base < s.n_spheres && !done; base += 64) {
+      const int j = base + lane;
+      const int jc = j < s.n_spheres ? j : s.n_spheres - 1;
+      const float4 a = cones[jc];
+      const float4 g = s.geom[jc];
+      uint64_t m = wave_mask((j < s.n_spheres) & cone_may_pass(wc, a));
+      while (m) {
+        const int k = (int)__builtin_ctzll(m);
+        m &= m - 1;
+        if (wave_any(!occ & (cone_excess(lane_read4(a, k), ux, uy, uz) >= 0.0f))) {
+          shadow_sphere(lane_read4(g, k), base + k, rr, lim, self, occ, first);
+          if (!wave_any(!occ)) {   // every lane of the wave is occluded
+            done = true;
+            break;
+          }
         }
       }
     }
-    c0 = n0;
-    c1 = n1;
-    if (!wave_any(!occ)) break;   // every lane of the wave is occluded
+  } else {
+    rt_v16 c0 = ld16(cones, 0), c1 = ld16(cones, 4);
+    for (int i = 0; i < s.n4; i += kGroup) {
+      rt_v16 n0 = ld16(cones, i + 8), n1 = ld16(cones, i + 12);
+#pragma unroll
+      for (int k = 0; k < kGroup; ++k) {
+        float4 a = part(k < 4 ? c0 : c1, k & 3);
+        if (!kPrefilter || wave_any(!occ & (cone_excess(a, ux, uy, uz) >= 0.0f)))
+          shadow_sphere(ld4(s.geom, i + k), i + k, rr, lim, self, occ, first);
+      }
+      c0 = n0;
+      c1 = n1;
+      if (!wave_any(!occ)) break;   // every lane of the wave is occluded
+    }
   }
-  if (occ) {
-    cnt.tests(first + 1, 0);
-    return true;
-  }
+  const bool by_sphere = act && occ;
+  int plane_hit = -1;
   Ray sr;
   sr.ox = f.px; sr.oy = f.py; sr.oz = f.pz;
   sr.dx = lx; sr.dy = ly; sr.dz = lz;
-  for (int j = 0; j < s.n_planes; ++j)
-    if (s.n_spheres + j != self && plane_root(ld4(s.pgeom, j), sr, s.t_min) < dist) {
-      cnt.tests(s.n_spheres, j + 1);
-      return true;
-    }
-  cnt.tests(s.n_spheres, s.n_planes);
-  return false;
+  for (int j = 0; j < s.n_planes; ++j) {
+    const bool hit = !occ && s.n_spheres + j != self && plane_root(ld4(s.pgeom, j), sr, s.t_min) < dist;
+    plane_hit = hit ? j : plane_hit;
+    occ = occ || hit;
+  }
+  if (act) {
+    if (by_sphere)
+      cnt.tests(first + 1, 0);
+    else if (plane_hit >= 0)
+      cnt.tests(s.n_spheres, plane_hit + 1);
+    else
+      cnt.tests(s.n_spheres, s.n_planes);
+  }
+  return occ;
 }
 
 // x^e for x > 0 as exp2(e log2 x); 0 otherwise.
@@ -397,9 +627,11 @@ __device__ __forceinline__ float spec_base(int model, float nx, float ny, float 
 
 // Light terms at a surface point: A = k_a + sum I (n.l), S = sum I k_s spec,
 // over lights with n.l > 0 and no occluder; returns the lit-light mask.
+// Only lanes with `on` take part (the others get a mask of 0); the shadow
+// rays of a light are traced while any lane of the wave needs one.
 template <bool kPrefilter = true, class Cnt = NoCount>
 __device__ __forceinline__ uint32_t light_terms(const SceneDev& s, const Surface& f, const Ray& r,
-                                                float& A, float& S, Cnt& cnt) {
+                                                bool on, float& A, float& S, Cnt& cnt) {
   A = s.ambient;
   S = 0.0f;
   uint32_t lit = 0;
@@ -413,9 +645,11 @@ __device__ __forceinline__ uint32_t light_terms(const SceneDev& s, const Surface
     ly *= inv;
     lz *= inv;
     float nl = dot3(f.nx, f.ny, f.nz, lx, ly, lz);
-    if (nl > 0.0f) {
-      cnt.ray(kCntShadow);
-      if (!occluded<kPrefilter>(s, l, q, f, lx, ly, lz, dist, cnt)) {
+    const bool act = on && nl > 0.0f;
+    if (wave_any(act)) {
+      if (act) cnt.ray(kCntShadow);
+      const bool occ = occluded<kPrefilter>(s, l, q, f, lx, ly, lz, dist, act, cnt);
+      if (act && !occ) {
         lit |= 1u << l;
         A = fmaf(q.w, nl, A);
         float x = spec_base(s.spec_model, f.nx, f.ny, f.nz, lx, ly, lz, -r.dx, -r.dy, -r.dz, nl);
@@ -457,71 +691,80 @@ struct PathState {
 
 // Segment k of a path: closest hit, light terms with shadow rays, colour
 // contribution T_k (A_k w_k a_k + S_k) (or T_k bg on a miss), then the mirror
-// ray when k < depth.  Returns the id hit; the path continues iff the id is
-// >= 0 and k < depth.  `sink.seg(k, id)` / `sink.lit(k, mask)` see the
-// segment.  Every kernel runs a segment through this one function.
+// ray when k < depth.  Only lanes with `alive` trace the segment; on return
+// `alive` says whether the path goes on (a hit below the bounce limit).
+// `sink.seg(k, id)` / `sink.lit(k, mask)` see the segment.  Every kernel runs
+// a segment through this one function, with all lanes of the wave executing.
 template <bool kFromEye, bool kPrefilter, class Sink, class Cnt>
 __device__ __forceinline__ int trace_segment(const SceneDev& s, PathState& ps, int k, int depth,
-                                             Sink& sink, Cnt& cnt) {
+                                             bool& alive, Sink& sink, Cnt& cnt) {
   float t;
   int id;
   if (kFromEye)
-    closest_hit<true, kPrefilter>(s, ps.r, t, id);
+    closest_hit<true, kPrefilter>(s, ps.r, alive, t, id);
   else
-    closest_hit<false, kPrefilter>(s, ps.r, t, id, ps.from_plane);
-  cnt.ray(k == 0 ? kCntPrimary : kCntReflection);
-  cnt.tests(s.n_spheres, s.n_planes);
-  sink.seg(k, id);
-  if (id < 0) {
-    ps.cr = fmaf(ps.T, s.bg_r, ps.cr);
-    ps.cg = fmaf(ps.T, s.bg_g, ps.cg);
-    ps.cb = fmaf(ps.T, s.bg_b, ps.cb);
-    return id;
+    closest_hit<false, kPrefilter>(s, ps.r, alive, t, id, ps.from_plane);
+  if (alive) {
+    cnt.ray(k == 0 ? kCntPrimary : kCntReflection);
+    cnt.tests(s.n_spheres, s.n_planes);
+    sink.seg(k, id);
+    if (id < 0) {
+      ps.cr = fmaf(ps.T, s.bg_r, ps.cr);
+      ps.cg = fmaf(ps.T, s.bg_g, ps.cg);
+      ps.cb = fmaf(ps.T, s.bg_b, ps.cb);
+    }
   }
-  Surface f = surface_at(s, ps.r, t, id);
-  float A, S;
-  sink.lit(k, light_terms<kPrefilter>(s, f, ps.r, A, S, cnt));
-  if (k < depth) {
-    float w = A * (1.0f - f.kr);
-    ps.cr = fmaf(ps.T, fmaf(w, f.ar, S), ps.cr);
-    ps.cg = fmaf(ps.T, fmaf(w, f.ag, S), ps.cg);
-    ps.cb = fmaf(ps.T, fmaf(w, f.ab, S), ps.cb);
-    ps.T = ps.T * (A * f.kr);
-    reflect_ray(ps.r, f);
-    ps.from_plane = id >= s.n_spheres ? id : -1;
-  } else {
-    ps.cr = fmaf(ps.T, fmaf(A, f.ar, S), ps.cr);
-    ps.cg = fmaf(ps.T, fmaf(A, f.ag, S), ps.cg);
-    ps.cb = fmaf(ps.T, fmaf(A, f.ab, S), ps.cb);
+  const bool hit = alive && id >= 0;
+  alive = hit && k < depth;
+  if (wave_any(hit)) {
+    // lanes without a hit shade primitive 0 along and keep nothing of it
+    Surface f = surface_at(s, ps.r, t, hit ? id : 0);
+    float A, S;
+    const uint32_t lit = light_terms<kPrefilter>(s, f, ps.r, hit, A, S, cnt);
+    if (hit) {
+      sink.lit(k, lit);
+      if (k < depth) {
+        float w = A * (1.0f - f.kr);
+        ps.cr = fmaf(ps.T, fmaf(w, f.ar, S), ps.cr);
+        ps.cg = fmaf(ps.T, fmaf(w, f.ag, S), ps.cg);
+        ps.cb = fmaf(ps.T, fmaf(w, f.ab, S), ps.cb);
+        ps.T = ps.T * (A * f.kr);
+        reflect_ray(ps.r, f);
+        ps.from_plane = id >= s.n_spheres ? id : -1;
+      } else {
+        ps.cr = fmaf(ps.T, fmaf(A, f.ar, S), ps.cr);
+        ps.cg = fmaf(ps.T, fmaf(A, f.ag, S), ps.cg);
+        ps.cb = fmaf(ps.T, fmaf(A, f.ab, S), ps.cb);
+      }
+    }
   }
   return id;
 }
 
-// The whole path of one pixel in one lane.  `sink.seg(k, id)` and
+// The whole path of one pixel in one lane; lanes with `live` false (outside
+// the image) run along without a path, so that every lane of the wave
+// executes the segment code together.  `sink.seg(k, id)` and
 // `sink.lit(k, mask)` see every traced segment; the caller marks untraced
-// segments.  Returns the number of segments traced.
+// segments.  Returns the number of segments traced (0 when not live).
 template <class Sink, class Cnt = NoCount, bool kPrefilter = true>
-__device__ __forceinline__ int trace_path(const SceneDev& s, Ray r, int depth, float& cr,
-                                          float& cg, float& cb, int& prim, Sink& sink,
+__device__ __forceinline__ int trace_path(const SceneDev& s, Ray r, int depth, bool live,
+                                          float& cr, float& cg, float& cb, int& prim, Sink& sink,
                                           Cnt&& cnt = Cnt()) {
   PathState ps;
   ps.r = r;
   ps.T = 1.0f;
   ps.cr = 0.0f; ps.cg = 0.0f; ps.cb = 0.0f;
   ps.from_plane = -1;
-  prim = trace_segment<true, kPrefilter>(s, ps, 0, depth, sink, cnt);
-  int k = 1;
-  if (prim >= 0 && depth > 0) {
-    for (; k <= depth; ++k) {
-      const int id = trace_segment<false, kPrefilter>(s, ps, k, depth, sink, cnt);
-      if (id < 0 || k == depth) {
-        ++k;
-        break;
-      }
-    }
+  bool alive = live;
+  prim = trace_segment<true, kPrefilter>(s, ps, 0, depth, alive, sink, cnt);
+  int traced = live ? 1 : 0;
+  for (int k = 1; k <= depth; ++k) {
+    if (!wave_any(alive)) break;
+    traced = alive ? k + 1 : traced;
+    trace_segment<false, kPrefilter>(s, ps, k, depth, alive, sink, cnt);
   }
   cr = ps.cr; cg = ps.cg; cb = ps.cb;
-  return k;
+  return traced;
 }
 
 }  // namespace rtk

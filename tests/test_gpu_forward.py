@@ -165,3 +165,63 @@ def test_prefilters_change_no_bits_small_scenes(rt, seed):
             imgs.append(rgb.cpu())
     for im in imgs[1:]:
         assert torch.equal(imgs[0], im)
+
+
+# Scenes chosen to drive every branch of the wave bounds: several 64-sphere
+# chunks with a ragged last one, dense boxes (many sphere-to-sphere mirror
+# rays, wide bundles), rotated cameras, ragged image sizes, a light inside a
+# sphere and an eye inside a sphere (cones that take every direction).
+VARIED = [
+    # seed, N, lights, box, W, H, depth, eye, yaw, pitch, light_in, eye_in
+    (0, 65, 1, "small", 201, 113, 6, (0.0, 0.0, 0.0), 0.0, 0.0, False, False),
+    (1, 100, 2, "wide", 160, 90, 4, (1.0, 1.5, 2.0), 20.0, -10.0, False, False),
+    (2, 129, 3, "small", 97, 131, 5, (0.0, 0.3, 0.0), -35.0, 5.0, True, False),
+    (3, 200, 4, "wide", 128, 72, 3, (-2.0, 0.0, 1.0), 60.0, 15.0, False, True),
+    (4, 300, 2, "small", 150, 100, 8, (0.5, 0.5, -3.0), 170.0, -20.0, True, True),
+    (5, 64, 1, "small", 64, 64, 4, (0.0, 5.0, -8.0), 0.0, -89.0, False, False),
+]
+
+
+@pytest.mark.parametrize("case", range(len(VARIED)))
+def test_wave_bounds_change_no_bits(rt, case):
+    seed, n, L, box, W, H, D, eye, yaw, pitch, light_in, eye_in = VARIED[case]
+    rng = np.random.default_rng(900 + seed)
+    b = scenegen.BOX_SMALL if box == "small" else ((-20.0, -1.0, -40.0), (20.0, 6.0, -2.0))
+    s = scenegen.random_scene(rng, n, L, box=b, spec_model=seed % 2)
+    if light_in:
+        s.light[0, :3] = s.sphere_geom[0, :3]
+    if eye_in:
+        eye = tuple(float(v) for v in s.sphere_geom[3, :3])
+    cam = Camera(eye=eye, yaw_deg=yaw, pitch_deg=pitch)
+    log("case", case, "N", n, "L", L, "size", W, H, "depth", D)
+    with rt.SceneHandle(s) as h:
+        out = []
+        for flags in ALL_FLAGS:
+            rgb = torch.empty((H, W, 3), device="cuda")
+            ids = torch.empty((H, W), dtype=torch.int32, device="cuda")
+            rec = rt.Records(W, H, D)
+            rt.rt_render_ex(h.handle, cam, W, H, D, rgb, ids, rec, flags)
+            torch.cuda.synchronize()
+            out.append((rgb.cpu(), ids.cpu(), rec.buf.cpu()))
+    for a, b2 in zip(out[0], out[1]):
+        assert torch.equal(a, b2)
+
+
+def test_wave_bounds_change_no_bits_batch_scenes(rt):
+    """All 64 scenes of the batch workload (4 to 1024 spheres in a small box,
+    so mirror rays often scatter over every direction): image, ids and
+    records are the same bits with and without the bounds."""
+    for i, wl in enumerate(scenegen.make_batch()):
+        W, H, D = wl.W, wl.H, wl.depth
+        log("case batch scene", i, wl.name)
+        with rt.SceneHandle(wl.scene) as h:
+            out = []
+            for flags in ALL_FLAGS:
+                rgb = torch.empty((H, W, 3), device="cuda")
+                ids = torch.empty((H, W), dtype=torch.int32, device="cuda")
+                rec = rt.Records(W, H, D)
+                rt.rt_render_ex(h.handle, wl.camera, W, H, D, rgb, ids, rec, flags)
+                torch.cuda.synchronize()
+                out.append((rgb.cpu(), ids.cpu(), rec.buf.cpu()))
+        for a, b2 in zip(out[0], out[1]):
+            assert torch.equal(a, b2), i
