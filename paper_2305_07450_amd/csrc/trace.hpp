@@ -157,13 +157,16 @@ __device__ __forceinline__ Ray primary_ray(const CameraDev& c, int x, int y) {
 // it does not cancel when the sphere is far away, and it is insensitive to
 // first order to |d| differing from 1 by rounding.  Returns |f|^2; the ray
 // meets the sphere iff |f|^2 <= r^2.
-__device__ __forceinline__ float sphere_ff(float4 g, const Ray& r, float& b) {
-  float ocx = r.ox - g.x, ocy = r.oy - g.y, ocz = r.oz - g.z;
+__device__ __forceinline__ float sphere_ff_oc(float ocx, float ocy, float ocz, const Ray& r,
+                                              float& b) {
   b = dot3(ocx, ocy, ocz, r.dx, r.dy, r.dz);
   float fx = fmaf(-b, r.dx, ocx);
   float fy = fmaf(-b, r.dy, ocy);
   float fz = fmaf(-b, r.dz, ocz);
   return dot3(fx, fy, fz, fx, fy, fz);
+}
+__device__ __forceinline__ float sphere_ff(float4 g, const Ray& r, float& b) {
+  return sphere_ff_oc(r.ox - g.x, r.oy - g.y, r.oz - g.z, r, b);
 }
 
 // Nearest root above t_min (the far root when the near one is not), or +inf.
@@ -175,10 +178,11 @@ __device__ __forceinline__ float sphere_root(float r2, float ff, float b, float 
   return t0 > t_min ? t0 : (t1 > t_min ? t1 : __builtin_inff());
 }
 
-// m.(o + t d) = h; a ray parallel to the plane misses.
+// m.(o + t d) = h; a ray parallel to the plane misses.  The quotient takes
+// the hardware reciprocal (1 ulp) instead of a correctly rounded division.
 __device__ __forceinline__ float plane_root(float4 g, const Ray& r, float t_min) {
   float den = dot3(g.x, g.y, g.z, r.dx, r.dy, r.dz);
-  float t = (g.w - dot3(g.x, g.y, g.z, r.ox, r.oy, r.oz)) / den;
+  float t = (g.w - dot3(g.x, g.y, g.z, r.ox, r.oy, r.oz)) * __builtin_amdgcn_rcpf(den);
   return (den != 0.0f && t > t_min) ? t : __builtin_inff();
 }
 
@@ -219,19 +223,47 @@ __device__ __forceinline__ float4 lane_read4(float4 v, int lane) {
   return make_float4(lane_read(v.x, lane), lane_read(v.y, lane), lane_read(v.z, lane),
                      lane_read(v.w, lane));
 }
-template <int kCtrl>
-__device__ __forceinline__ float dpp(float v) {
-  return __builtin_bit_cast(float,
-                            __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), kCtrl, 0xf, 0xf, true));
+// Minimum over all 64 lanes (all executing), in every lane.  The floats are
+// mapped to integers of the same order (the magnitude bits of negatives
+// flipped), so each step is one integer min with a DPP operand: quad swaps,
+// half-row and row mirrors within each row of 16, then the four row results.
+__device__ __forceinline__ int float_order(float v) {
+  const int i = __builtin_bit_cast(int, v);
+  return i ^ ((i >> 31) & 0x7fffffff);
 }
-// Minimum over all 64 lanes (all executing), in every lane: quad swaps, half-row
-// and row mirrors within each row of 16, then the four row results.
-__device__ __forceinline__ float wave_min(float v) {
-  v = fminf(v, dpp<0xB1>(v));    // quad_perm [1, 0, 3, 2]
-  v = fminf(v, dpp<0x4E>(v));    // quad_perm [2, 3, 0, 1]
-  v = fminf(v, dpp<0x141>(v));   // row_half_mirror
-  v = fminf(v, dpp<0x140>(v));   // row_mirror
-  return fminf(fminf(lane_read(v, 0), lane_read(v, 16)), fminf(lane_read(v, 32), lane_read(v, 48)));
+__device__ __forceinline__ float order_float(int i) {
+  return __builtin_bit_cast(float, i ^ ((i >> 31) & 0x7fffffff));
+}
+template <int kCtrl>
+__device__ __forceinline__ int dpp_min(int v) {
+  return min(v, __builtin_amdgcn_mov_dpp(v, kCtrl, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float wave_min(float x) {
+  int v = float_order(x);
+  v = dpp_min<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+  v = dpp_min<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+  v = dpp_min<0x141>(v);   // row_half_mirror
+  v = dpp_min<0x140>(v);   // row_mirror
+  const int a = min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16));
+  const int b = min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48));
+  return order_float(min(a, b));
+}
+
+// Exact test of sphere i against the ray, given oc = o - c and r^2; keeps
+// the nearest.
+__device__ __forceinline__ void test_sphere_oc(float ocx, float ocy, float ocz, float r2, int i,
+                                               const Ray& r, float tmin, float& t_best,
+                                               int& id_best) {
+  float b;
+  float ff = sphere_ff_oc(ocx, ocy, ocz, r, b);
+  const bool in = ff <= r2;
+  if (wave_any(in)) {
+    // lanes that miss compute a harmless root and are masked by `better`
+    float t = sphere_root(r2, in ? ff : r2, b, tmin);
+    const bool better = in && t < t_best;
+    t_best = better ? t : t_best;
+    id_best = better ? i : id_best;
+  }
 }
 
 // Exact test of sphere i (geometry g) against the ray; keeps the nearest.
@@ -251,6 +283,31 @@ __device__ __forceinline__ void test_sphere(float4 g, int i, const Ray& r, float
 
 __device__ __forceinline__ float4 part(const rt_v16& v, int k) {
   return make_float4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
+}
+
+// Scalar-load scan of a sphere table (geom or cones): calls f(i, entry i) for
+// i = 0 .. n4-1 in ascending order, reading kScanBlocks 64-byte blocks (4
+// entries each) per group and fetching the next group while the current one
+// is tested; stops after a group once done() holds.  The tables hold one
+// padding group of kGroup entries past n4, which covers the look-ahead.
+constexpr int kScanBlocks = 1;
+static_assert(4 * kScanBlocks <= kGroup && kGroup % (4 * kScanBlocks) == 0, "scan look-ahead");
+
+template <class F, class Done>
+__device__ __forceinline__ void scan_spheres(const float4* tab, int n4, F&& f, Done&& done) {
+  rt_v16 cur[kScanBlocks];
+#pragma unroll
+  for (int b = 0; b < kScanBlocks; ++b) cur[b] = ld16(tab, 4 * b);
+  for (int i = 0; i < n4; i += 4 * kScanBlocks) {
+    rt_v16 nxt[kScanBlocks];
+#pragma unroll
+    for (int b = 0; b < kScanBlocks; ++b) nxt[b] = ld16(tab, i + 4 * (kScanBlocks + b));
+#pragma unroll
+    for (int k = 0; k < 4 * kScanBlocks; ++k) f(i + k, part(cur[k >> 2], k & 3));
+#pragma unroll
+    for (int b = 0; b < kScanBlocks; ++b) cur[b] = nxt[b];
+    if (done()) break;
+  }
 }
 
 // a.u - w for a cone (a, w): >= 0 inside the cone (with the cone's margin).
@@ -416,27 +473,26 @@ __device__ __forceinline__ void closest_hit(const SceneDev& s, const Ray& r, boo
         const int jc = j < s.n_spheres ? j : s.n_spheres - 1;
         const float4 a = s.eye_cone[jc];
         const float4 g = s.geom[jc];
+        // every lane's ray starts at the eye: o - c of this lane's sphere is
+        // the o - c every lane would form for it
+        const float ocx = r.ox - g.x, ocy = r.oy - g.y, ocz = r.oz - g.z;
         uint64_t m = wave_mask((j < s.n_spheres) & cone_may_pass(wc, a));
         while (m) {
           const int k = (int)__builtin_ctzll(m);
           m &= m - 1;
           if (wave_any(live & (cone_excess(lane_read4(a, k), r.dx, r.dy, r.dz) >= 0.0f)))
-            test_sphere(lane_read4(g, k), base + k, r, tmin, t_best, id_best);
+            test_sphere_oc(lane_read(ocx, k), lane_read(ocy, k), lane_read(ocz, k),
+                           lane_read(g.w, k), base + k, r, tmin, t_best, id_best);
         }
       }
     } else {
-      rt_v16 c0 = ld16(s.eye_cone, 0), c1 = ld16(s.eye_cone, 4);
-      for (int i = 0; i < s.n4; i += kGroup) {
-        rt_v16 n0 = ld16(s.eye_cone, i + 8), n1 = ld16(s.eye_cone, i + 12);
-#pragma unroll
-        for (int k = 0; k < kGroup; ++k) {
-          float4 a = part(k < 4 ? c0 : c1, k & 3);
-          if (wave_any(live & (cone_excess(a, r.dx, r.dy, r.dz) >= 0.0f)))
-            test_sphere(ld4(s.geom, i + k), i + k, r, tmin, t_best, id_best);
-        }
-        c0 = n0;
-        c1 = n1;
-      }
+      scan_spheres(
+          s.eye_cone, s.n4,
+          [&](int i, float4 a) {
+            if (wave_any(live & (cone_excess(a, r.dx, r.dy, r.dz) >= 0.0f)))
+              test_sphere(ld4(s.geom, i), i, r, tmin, t_best, id_best);
+          },
+          [] { return false; });
     }
   } else {
     const WaveBundle wb = (!kFromEye && kPrefilter) ? wave_bundle(live, r) : WaveBundle{};
@@ -454,15 +510,9 @@ __device__ __forceinline__ void closest_hit(const SceneDev& s, const Ray& r, boo
         }
       }
     } else {
-      rt_v16 c0 = ld16(s.geom, 0), c1 = ld16(s.geom, 4);
-      for (int i = 0; i < s.n4; i += kGroup) {
-        rt_v16 n0 = ld16(s.geom, i + 8), n1 = ld16(s.geom, i + 12);
-#pragma unroll
-        for (int k = 0; k < kGroup; ++k)
-          test_sphere(part(k < 4 ? c0 : c1, k & 3), i + k, r, tmin, t_best, id_best);
-        c0 = n0;
-        c1 = n1;
-      }
+      scan_spheres(
+          s.geom, s.n4, [&](int i, float4 g) { test_sphere(g, i, r, tmin, t_best, id_best); },
+          [] { return false; });
     }
   }
   for (int j = 0; j < s.n_planes; ++j) {
@@ -476,6 +526,20 @@ __device__ __forceinline__ void closest_hit(const SceneDev& s, const Ray& r, boo
 
 // Exact occlusion test of sphere i (geometry g) on the reversed shadow ray rr
 // for the lanes not yet occluded; records the first occluder.
+__device__ __forceinline__ void shadow_sphere_oc(float ocx, float ocy, float ocz, float r2, int i,
+                                                 const Ray& rr, float lim, int self, bool& occ,
+                                                 int& first) {
+  float b;
+  float ff = sphere_ff_oc(ocx, ocy, ocz, rr, b);
+  const bool in = !occ & (ff <= r2) & (i != self);
+  if (wave_any(in)) {
+    float sq = fsqrt(in ? r2 - ff : 0.0f);
+    float t0 = -b - sq, t1 = -b + sq;
+    const bool hit = in && ((t0 > 0.0f && t0 < lim) || (t1 > 0.0f && t1 < lim));
+    first = hit ? i : first;
+    occ = occ || hit;
+  }
+}
 __device__ __forceinline__ void shadow_sphere(float4 g, int i, const Ray& rr, float lim, int self,
                                               bool& occ, int& first) {
   float b;
@@ -527,12 +591,15 @@ __device__ __forceinline__ bool occluded(const SceneDev& s, int l, float4 q, con
       const int jc = j < s.n_spheres ? j : s.n_spheres - 1;
       const float4 a = cones[jc];
       const float4 g = s.geom[jc];
+      // every reversed shadow ray starts at the light (see closest_hit)
+      const float ocx = q.x - g.x, ocy = q.y - g.y, ocz = q.z - g.z;
       uint64_t m = wave_mask((j < s.n_spheres) & cone_may_pass(wc, a));
       while (m) {
         const int k = (int)__builtin_ctzll(m);
         m &= m - 1;
         if (wave_any(!occ & (cone_excess(lane_read4(a, k), ux, uy, uz) >= 0.0f))) {
-          shadow_sphere(lane_read4(g, k), base + k, rr, lim, self, occ, first);
+          shadow_sphere_oc(lane_read(ocx, k), lane_read(ocy, k), lane_read(ocz, k),
+                           lane_read(g.w, k), base + k, rr, lim, self, occ, first);
           if (!wave_any(!occ)) {   // every lane of the wave is occluded
             done = true;
             break;
@@ -541,19 +608,13 @@ __device__ __forceinline__ bool occluded(const SceneDev& s, int l, float4 q, con
       }
     }
   } else {
-    rt_v16 c0 = ld16(cones, 0), c1 = ld16(cones, 4);
-    for (int i = 0; i < s.n4; i += kGroup) {
-      rt_v16 n0 = ld16(cones, i + 8), n1 = ld16(cones, i + 12);
-#pragma unroll
-      for (int k = 0; k < kGroup; ++k) {
-        float4 a = part(k < 4 ? c0 : c1, k & 3);
-        if (!kPrefilter || wave_any(!occ & (cone_excess(a, ux, uy, uz) >= 0.0f)))
-          shadow_sphere(ld4(s.geom, i + k), i + k, rr, lim, self, occ, first);
-      }
-      c0 = n0;
-      c1 = n1;
-      if (!wave_any(!occ)) break;   // every lane of the wave is occluded
-    }
+    scan_spheres(
+        cones, s.n4,
+        [&](int i, float4 a) {
+          if (!kPrefilter || wave_any(!occ & (cone_excess(a, ux, uy, uz) >= 0.0f)))
+            shadow_sphere(ld4(s.geom, i), i, rr, lim, self, occ, first);
+        },
+        [&] { return !wave_any(!occ); });   // every lane of the wave is occluded
   }
   const bool by_sphere = act && occ;
   int plane_hit = -1;
@@ -576,9 +637,12 @@ __device__ __forceinline__ bool occluded(const SceneDev& s, int l, float4 q, con
   return occ;
 }
 
-// x^e for x > 0 as exp2(e log2 x); 0 otherwise.
+// x^e for x > 0 as exp2(e log2 x); 0 otherwise.  The hardware base-2
+// logarithm and exponential (about 1 ulp) without the library's denormal
+// scaling: x <= 1 here, and results below 2^-126 only lose digits that are
+// far below the image's precision.
 __device__ __forceinline__ float spec_pow(float x, float e) {
-  return x > 0.0f ? exp2f(e * log2f(x)) : 0.0f;
+  return x > 0.0f ? __builtin_amdgcn_exp2f(e * __builtin_amdgcn_logf(x)) : 0.0f;
 }
 
 
