@@ -322,10 +322,11 @@ __device__ __forceinline__ float cone_excess(float4 a, float ux, float uy, float
 // lane per sphere decide, for 64 spheres at once, whether any lane can pass
 // that sphere's own cone test; the other spheres are skipped for the wave.
 //
-// Axis: the direction of the first participating lane.  cos(phi): the least
-// e.u over the participating lanes, lowered by 2e-6, which covers the FP32
-// error of the 3-term dot products of near-unit vectors, so the true angle
-// between e and every u is at most phi.
+// Axis: the direction of the first participating lane, or for a wider spread
+// a bisector (refined_axis).  cos(phi): the least e.u over the participating
+// lanes, lowered by 2e-6, which covers the FP32 error of the 3-term dot
+// products of near-unit vectors, so the true angle between e and every u is
+// at most phi.
 struct WaveCone {
   float ex, ey, ez;
   float c, s;   // cos(phi), sin(phi)
@@ -334,6 +335,44 @@ struct WaveCone {
 
 // Widest wave cone still worth its cost (cos of the half-angle).
 constexpr float kWaveConeMinCos = 0.5f;
+
+// Least e.u over the lanes with `take` (2 if none), and a lane attaining it.
+__device__ __forceinline__ float least_dot(bool take, float ex, float ey, float ez, float ux,
+                                           float uy, float uz, int& at) {
+  const float d = take ? dot3(ex, ey, ez, ux, uy, uz) : 2.0f;
+  const float m = wave_min(d);
+  const uint64_t hit = wave_mask(take & (d == m));
+  at = hit ? (int)__builtin_ctzll(hit) : 0;
+  return m;
+}
+
+// Cones wider than this (cos of the half-angle) get a second axis: the
+// bisector of the first one and the direction farthest from it, which about
+// halves the angle for an elongated spread; the narrower of the two is kept.
+constexpr float kRefineCos = 0.9995f;
+
+// Axis e (unit, in/out) and the least e.u over the lanes with `take`.
+__device__ __forceinline__ float refined_axis(bool take, float ux, float uy, float uz, float& ex,
+                                              float& ey, float& ez) {
+  int far;
+  float c = least_dot(take, ex, ey, ez, ux, uy, uz, far);
+  if (c < kRefineCos) {
+    const float sx = ex + lane_read(ux, far), sy = ey + lane_read(uy, far),
+                sz = ez + lane_read(uz, far);
+    const float n2 = dot3(sx, sy, sz, sx, sy, sz);
+    if (n2 > 1e-6f) {
+      const float inv = frsq(n2);
+      const float fx = sx * inv, fy = sy * inv, fz = sz * inv;
+      int unused;
+      const float c2 = least_dot(take, fx, fy, fz, ux, uy, uz, unused);
+      if (c2 > c) {
+        ex = fx; ey = fy; ez = fz;
+        c = c2;
+      }
+    }
+  }
+  return c;
+}
 
 __device__ __forceinline__ WaveCone wave_cone(bool take, float ux, float uy, float uz) {
   WaveCone w;
@@ -347,7 +386,7 @@ __device__ __forceinline__ WaveCone wave_cone(bool take, float ux, float uy, flo
     w.ex = lane_read(ux, f);
     w.ey = lane_read(uy, f);
     w.ez = lane_read(uz, f);
-    const float c = wave_min(take ? dot3(w.ex, w.ey, w.ez, ux, uy, uz) : 2.0f) - 2e-6f;
+    const float c = refined_axis(take, ux, uy, uz, w.ex, w.ey, w.ez) - 2e-6f;
     w.c = c;
     w.s = fsqrt(fmaxf(fmaf(-c, c, 1.0f), 0.0f));
     w.on = c > kWaveConeMinCos;
@@ -371,9 +410,10 @@ __device__ __forceinline__ bool cone_may_pass(const WaveCone& wc, float4 a) {
 }
 
 // ---- Wave bundles: one bound for mirror rays with different origins --------
-// Origins in a ball (centre m = the first participating lane's origin, radius
-// rho = the largest distance to it, raised by 1e-5 relative for rounding) and
-// directions in a wave cone (e, phi), with phi < 90 degrees.  Every point
+// Origins in a ball (centre m: the midpoint of the first participating lane's
+// origin and the origin farthest from it; radius rho: the largest distance to
+// m, raised by 1e-5 relative for rounding) and directions in a wave cone
+// (e, phi), with phi < 90 degrees.  Every point
 // o + t d with t >= 0 then lies in the cone with apex v = m - e rho / sin(phi),
 // axis e and half-angle phi: that cone holds the ball (the ball's distance to
 // its side is rho) and, being convex, every step from a point of it along a
@@ -400,14 +440,25 @@ __device__ __forceinline__ WaveBundle wave_bundle(bool take, const Ray& r) {
   b.reach = 0.0f;
   if (b.on) {
     const int f = (int)__builtin_ctzll(m);
-    const float mx = lane_read(r.ox, f), my = lane_read(r.oy, f), mz = lane_read(r.oz, f);
+    float mx = lane_read(r.ox, f), my = lane_read(r.oy, f), mz = lane_read(r.oz, f);
     b.ex = lane_read(r.dx, f);
     b.ey = lane_read(r.dy, f);
     b.ez = lane_read(r.dz, f);
-    const float qx = r.ox - mx, qy = r.oy - my, qz = r.oz - mz;
-    const float rho2 = wave_min(take ? -dot3(qx, qy, qz, qx, qy, qz) : 0.0f);
+    // ball: first origin, then the midpoint of it and the origin farthest away
+    float qx = r.ox - mx, qy = r.oy - my, qz = r.oz - mz;
+    float nq2 = take ? -dot3(qx, qy, qz, qx, qy, qz) : 0.0f;
+    float rho2 = wave_min(nq2);
+    if (rho2 < 0.0f) {
+      const uint64_t hit = wave_mask(take & (nq2 == rho2));
+      const int h = hit ? (int)__builtin_ctzll(hit) : f;
+      mx = 0.5f * (mx + lane_read(r.ox, h));
+      my = 0.5f * (my + lane_read(r.oy, h));
+      mz = 0.5f * (mz + lane_read(r.oz, h));
+      qx = r.ox - mx; qy = r.oy - my; qz = r.oz - mz;
+      rho2 = wave_min(take ? -dot3(qx, qy, qz, qx, qy, qz) : 0.0f);
+    }
     const float rho = fmaf(fsqrt(-rho2), 1.00001f, 1e-6f);
-    float c = wave_min(take ? dot3(b.ex, b.ey, b.ez, r.dx, r.dy, r.dz) : 2.0f) - 2e-6f;
+    float c = refined_axis(take, r.dx, r.dy, r.dz, b.ex, b.ey, b.ez) - 2e-6f;
     // decided on phi itself: sin(phi) is also small when phi is near 180 degrees
     b.on = c > kBundleMinCos;
     float sn = fsqrt(fmaxf(fmaf(-c, c, 1.0f), 0.0f));
