@@ -26,8 +26,24 @@ constexpr int kTileA = 8;
 constexpr int kBlockA = 16;        // pixels per workgroup tile edge (2 x 2 wave tiles)
 constexpr int kLdsFloats = 16384;  // 64 KiB of accumulators per workgroup
 
+// Sum over the 64 lanes in a fixed order, so that runs repeat bit for bit.
+// With every lane executing: DPP adds within each row of 16 (quad swaps, half
+// mirror, mirror; both lanes of a pair add the same two values, so a row ends
+// with one value), then the four rows in a fixed order.  Otherwise an xor
+// butterfly through the LDS crossbar.  Every lane gets the sum.
+template <int kCtrl>
+__device__ __forceinline__ float dpp_add(float v) {
+  return v + __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), kCtrl,
+                                                                0xf, 0xf, true));
+}
 __device__ __forceinline__ float wave_sum(float v) {
-  // xor butterfly: every lane ends with the same bits, in a fixed order
+  if (wave_full()) {
+    v = dpp_add<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+    v = dpp_add<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+    v = dpp_add<0x141>(v);   // row_half_mirror
+    v = dpp_add<0x140>(v);   // row_mirror
+    return (lane_read(v, 0) + lane_read(v, 16)) + (lane_read(v, 32) + lane_read(v, 48));
+  }
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
