@@ -286,19 +286,20 @@ __device__ __forceinline__ float4 part(const rt_v16& v, int k) {
 }
 
 // Scalar-load scan of a sphere table (geom or cones): calls f(i, entry i) for
-// i = 0 .. n4-1 in ascending order, reading kScanBlocks 64-byte blocks (4
-// entries each) per group and fetching the next group while the current one
-// is tested; stops after a group once done() holds.  The tables hold one
-// padding group of kGroup entries past n4, which covers the look-ahead.
+// i = lo .. hi-1 in ascending order (lo a multiple of 4, hi <= n4), reading
+// kScanBlocks 64-byte blocks (4 entries each) per group and fetching the next
+// group while the current one is tested; stops after a group once done()
+// holds.  The tables hold one padding group of kGroup entries past n4, which
+// covers the look-ahead and a last group that runs past hi.
 constexpr int kScanBlocks = 1;
 static_assert(4 * kScanBlocks <= kGroup && kGroup % (4 * kScanBlocks) == 0, "scan look-ahead");
 
 template <class F, class Done>
-__device__ __forceinline__ void scan_spheres(const float4* tab, int n4, F&& f, Done&& done) {
+__device__ __forceinline__ void scan_range(const float4* tab, int lo, int hi, F&& f, Done&& done) {
   rt_v16 cur[kScanBlocks];
 #pragma unroll
-  for (int b = 0; b < kScanBlocks; ++b) cur[b] = ld16(tab, 4 * b);
-  for (int i = 0; i < n4; i += 4 * kScanBlocks) {
+  for (int b = 0; b < kScanBlocks; ++b) cur[b] = ld16(tab, lo + 4 * b);
+  for (int i = lo; i < hi; i += 4 * kScanBlocks) {
     rt_v16 nxt[kScanBlocks];
 #pragma unroll
     for (int b = 0; b < kScanBlocks; ++b) nxt[b] = ld16(tab, i + 4 * (kScanBlocks + b));
@@ -308,6 +309,10 @@ __device__ __forceinline__ void scan_spheres(const float4* tab, int n4, F&& f, D
     for (int b = 0; b < kScanBlocks; ++b) cur[b] = nxt[b];
     if (done()) break;
   }
+}
+template <class F, class Done>
+__device__ __forceinline__ void scan_spheres(const float4* tab, int n4, F&& f, Done&& done) {
+  scan_range(tab, 0, n4, f, done);
 }
 
 // a.u - w for a cone (a, w): >= 0 inside the cone (with the cone's margin).
@@ -330,7 +335,8 @@ __device__ __forceinline__ float cone_excess(float4 a, float ux, float uy, float
 struct WaveCone {
   float ex, ey, ez;
   float c, s;   // cos(phi), sin(phi)
-  bool on;      // usable: all lanes executing, some participate, phi small enough
+  bool full;    // all lanes executing and some participate
+  bool on;      // full, and phi small enough to be worth testing against
 };
 
 // Widest wave cone still worth its cost (cos of the half-angle).
@@ -377,7 +383,8 @@ __device__ __forceinline__ float refined_axis(bool take, float ux, float uy, flo
 __device__ __forceinline__ WaveCone wave_cone(bool take, float ux, float uy, float uz) {
   WaveCone w;
   const uint64_t m = wave_mask(take);
-  w.on = m != 0 && wave_full();
+  w.full = m != 0 && wave_full();
+  w.on = w.full;
   w.ex = w.ey = w.ez = 0.0f;
   w.c = -1.0f;
   w.s = 0.0f;
@@ -424,7 +431,8 @@ struct WaveBundle {
   float ex, ey, ez;   // axis
   float c, s;         // cos(phi), sin(phi)
   float reach;        // rho / sin(phi) + rho: farthest origin from the apex
-  bool on;
+  bool full;          // all lanes executing and some participate
+  bool on;            // full, and phi below 60 degrees
 };
 
 // Widest bundle still worth its cost (cos of the half-angle).
@@ -433,7 +441,8 @@ constexpr float kBundleMinCos = 0.5f;
 __device__ __forceinline__ WaveBundle wave_bundle(bool take, const Ray& r) {
   WaveBundle b;
   const uint64_t m = wave_mask(take);
-  b.on = m != 0 && wave_full();
+  b.full = m != 0 && wave_full();
+  b.on = b.full;
   b.vx = b.vy = b.vz = b.ex = b.ey = b.ez = 0.0f;
   b.c = -1.0f;
   b.s = 0.0f;
@@ -494,6 +503,78 @@ __device__ __forceinline__ bool sphere_may_meet(const WaveBundle& b, float4 g, f
   return (sb >= 1.0f) | (b.c + cb <= 1e-6f) | (ca >= thr - 1e-5f);
 }
 
+// ---- Transposed tests for waves with few live rays -------------------------
+// A wave whose bound keeps many spheres but has few live rays (later bounces)
+// turns the loop around: for each live ray q in turn, lane j tests sphere
+// base + j against ray q (read from lane q), and a wave minimum or ballot
+// folds the 64 results into lane q.  Each pair runs the same arithmetic as in
+// the per-lane loops, so the results are the same bits.  Per 64 spheres a
+// ray costs about kTransHitCost VALU operations in the closest-hit search and
+// kTransShadowCost in a shadow test, against about kLaneHitCost and
+// kLaneShadowCost per candidate sphere in the per-lane loops.
+constexpr int kTransHitCost = 45, kLaneHitCost = 20;
+constexpr int kTransShadowCost = 30, kLaneShadowCost = 10;
+constexpr bool kTransposedHit = true, kTransposedShadow = true;
+
+// Nearest root over the spheres base + j (j in `cand`, geometry g in lane j)
+// for every ray of `rays`; strict < against each ray's running best, and the
+// lowest id among equal roots, as the ascending per-lane scan gives.
+__device__ __forceinline__ void transposed_hit(float4 g, uint64_t cand, int base, uint64_t rays,
+                                               const Ray& r, float tmin, float& t_best,
+                                               int& id_best) {
+  const int lane = __lane_id();
+  const bool mine = (cand >> lane) & 1u;
+  while (rays) {
+    const int q = (int)__builtin_ctzll(rays);
+    rays &= rays - 1;
+    Ray rq;
+    rq.ox = lane_read(r.ox, q); rq.oy = lane_read(r.oy, q); rq.oz = lane_read(r.oz, q);
+    rq.dx = lane_read(r.dx, q); rq.dy = lane_read(r.dy, q); rq.dz = lane_read(r.dz, q);
+    float b;
+    const float ff = sphere_ff(g, rq, b);
+    const bool in = mine & (ff <= g.w);
+    const float t = in ? sphere_root(g.w, ff, b, tmin) : __builtin_inff();
+    const float tm = wave_min(t);
+    if (tm < __builtin_inff()) {
+      const int k = (int)__builtin_ctzll(wave_mask(t == tm));
+      const bool better = (lane == q) & (tm < t_best);
+      t_best = better ? tm : t_best;
+      id_best = better ? base + k : id_best;
+    }
+  }
+}
+
+// Shadow occlusion of every not yet occluded lane by the spheres base + j
+// (j in `cand`; o - c and r^2 of the reversed ray in lane j); records the
+// first occluder, as the ascending per-lane scan does.
+__device__ __forceinline__ void transposed_shadow(float ocx, float ocy, float ocz, float r2,
+                                                  uint64_t cand, int base, const Ray& rr,
+                                                  float lim, int self, bool& occ, int& first) {
+  const int lane = __lane_id();
+  const bool mine = (cand >> lane) & 1u;
+  uint64_t rays = wave_mask(!occ);
+  while (rays) {
+    const int q = (int)__builtin_ctzll(rays);
+    rays &= rays - 1;
+    Ray rq = rr;   // the origin is the light for every lane
+    rq.dx = lane_read(rr.dx, q); rq.dy = lane_read(rr.dy, q); rq.dz = lane_read(rr.dz, q);
+    const float limq = lane_read(lim, q);
+    const int selfq = __builtin_amdgcn_readlane(self, q);
+    float b;
+    const float ff = sphere_ff_oc(ocx, ocy, ocz, rq, b);
+    const bool in = mine & (ff <= r2) & (base + lane != selfq);
+    const float sq = fsqrt(in ? r2 - ff : 0.0f);
+    const float t0 = -b - sq, t1 = -b + sq;
+    const bool hit = in && ((t0 > 0.0f && t0 < limq) || (t1 > 0.0f && t1 < limq));
+    const uint64_t h = wave_mask(hit);
+    if (h) {
+      const bool me = lane == q;
+      first = me ? base + (int)__builtin_ctzll(h) : first;
+      occ = occ | me;
+    }
+  }
+}
+
 // Closest hit over every primitive: smallest root, ties to the lower id
 // (strict < while scanning ids in ascending order).  `from_plane` is the
 // plane a mirror ray leaves (-1 otherwise): a ray reflected off a plane moves
@@ -547,17 +628,32 @@ __device__ __forceinline__ void closest_hit(const SceneDev& s, const Ray& r, boo
     }
   } else {
     const WaveBundle wb = (!kFromEye && kPrefilter) ? wave_bundle(live, r) : WaveBundle{};
-    if (!kFromEye && kPrefilter && wb.on) {
+    if (!kFromEye && kPrefilter && wb.full) {
+      // per 64 spheres: the bundle's candidates, then the cheapest of the
+      // transposed test, the per-lane candidate loop and the scalar scan
       const int lane = __lane_id();
+      const uint64_t rays = wave_mask(live);
+      const int n_rays = __builtin_popcountll(rays);
       for (int base = 0; base < s.n_spheres; base += 64) {
         const int j = base + lane;
         const int jc = j < s.n_spheres ? j : s.n_spheres - 1;
         const float4 g = s.geom[jc];
-        uint64_t m = wave_mask((j < s.n_spheres) & sphere_may_meet(wb, g, s.rad[jc].x));
-        while (m) {
-          const int k = (int)__builtin_ctzll(m);
-          m &= m - 1;
-          test_sphere(lane_read4(g, k), base + k, r, tmin, t_best, id_best);
+        bool cand = j < s.n_spheres;
+        if (wb.on) cand = cand & sphere_may_meet(wb, g, s.rad[jc].x);
+        uint64_t m = wave_mask(cand);
+        if (kTransposedHit && n_rays * kTransHitCost < __builtin_popcountll(m) * kLaneHitCost) {
+          transposed_hit(g, m, base, rays, r, tmin, t_best, id_best);
+        } else if (wb.on) {
+          while (m) {
+            const int k = (int)__builtin_ctzll(m);
+            m &= m - 1;
+            test_sphere(lane_read4(g, k), base + k, r, tmin, t_best, id_best);
+          }
+        } else {
+          scan_range(
+              s.geom, base, min(base + 64, s.n4),
+              [&](int i, float4 gi) { test_sphere(gi, i, r, tmin, t_best, id_best); },
+              [] { return false; });
         }
       }
     } else {
@@ -620,7 +716,7 @@ __device__ __forceinline__ void shadow_sphere(float4 g, int i, const Ray& rr, fl
 // n.l > 0, i.e. it leaves that convex surface outwards and cannot meet it
 // again, so its test is skipped: in exact arithmetic it never occludes, and
 // skipping it keeps FP32 rounding of p from re-hitting it.
-template <bool kPrefilter, class Cnt>
+template <bool kPrefilter, bool kDense, class Cnt>
 __device__ __forceinline__ bool occluded(const SceneDev& s, int l, float4 q, const Surface& f,
                                          float lx, float ly, float lz, float dist, bool act,
                                          Cnt& cnt) {
@@ -634,7 +730,9 @@ __device__ __forceinline__ bool occluded(const SceneDev& s, int l, float4 q, con
   rr.ox = q.x; rr.oy = q.y; rr.oz = q.z;
   rr.dx = ux; rr.dy = uy; rr.dz = uz;
   const WaveCone wc = kPrefilter ? wave_cone(act, ux, uy, uz) : WaveCone{};
-  if (kPrefilter && wc.on) {
+  if (kPrefilter && kDense && wc.on) {
+    // shadow rays of primary hits: dense, coherent waves; the wave cone's
+    // candidates run the per-lane cone test
     const int lane = __lane_id();
     bool done = false;
     for (int base = 0; base < s.n_spheres && !done; base += 64) {
@@ -656,6 +754,51 @@ __device__ __forceinline__ bool occluded(const SceneDev& s, int l, float4 q, con
             break;
           }
         }
+      }
+    }
+  } else if (kPrefilter && !kDense && wc.full) {
+    // shadow rays of mirror hits: per 64 spheres, the wave cone's candidates,
+    // then the cheapest of the transposed test, the per-lane candidate loop
+    // and the scalar scan
+    const int lane = __lane_id();
+    bool done = false;
+    for (int base = 0; base < s.n_spheres && !done; base += 64) {
+      const int j = base + lane;
+      const int jc = j < s.n_spheres ? j : s.n_spheres - 1;
+      const float4 a = cones[jc];
+      const float4 g = s.geom[jc];
+      // every reversed shadow ray starts at the light (see closest_hit)
+      const float ocx = q.x - g.x, ocy = q.y - g.y, ocz = q.z - g.z;
+      bool cand = j < s.n_spheres;
+      if (wc.on) cand = cand & cone_may_pass(wc, a);
+      uint64_t m = wave_mask(cand);
+      const int n_rays = __builtin_popcountll(wave_mask(!occ));
+      if (kTransposedShadow &&
+          n_rays * kTransShadowCost < __builtin_popcountll(m) * kLaneShadowCost) {
+        transposed_shadow(ocx, ocy, ocz, g.w, m, base, rr, lim, self, occ, first);
+        done = !wave_any(!occ);
+      } else if (wc.on) {
+        while (m) {
+          const int k = (int)__builtin_ctzll(m);
+          m &= m - 1;
+          if (wave_any(!occ & (cone_excess(lane_read4(a, k), ux, uy, uz) >= 0.0f))) {
+            shadow_sphere_oc(lane_read(ocx, k), lane_read(ocy, k), lane_read(ocz, k),
+                             lane_read(g.w, k), base + k, rr, lim, self, occ, first);
+            if (!wave_any(!occ)) {   // every lane of the wave is occluded
+              done = true;
+              break;
+            }
+          }
+        }
+      } else {
+        scan_range(
+            cones, base, min(base + 64, s.n4),
+            [&](int i, float4 ai) {
+              if (wave_any(!occ & (cone_excess(ai, ux, uy, uz) >= 0.0f)))
+                shadow_sphere(ld4(s.geom, i), i, rr, lim, self, occ, first);
+            },
+            [&] { return !wave_any(!occ); });
+        done = !wave_any(!occ);
       }
     }
   } else {
@@ -697,7 +840,10 @@ __device__ __forceinline__ float spec_pow(float x, float e) {
 }
 
 
-__device__ __forceinline__ Surface surface_at(const SceneDev& s, const Ray& r, float t, int id) {
+// Hit point, unit normal and id; the material is left for surface_at or the
+// caller to load (the render path loads it after the shadow rays, so that it
+// is not held in registers across them).
+__device__ __forceinline__ Surface surface_geom(const SceneDev& s, const Ray& r, float t, int id) {
   Surface f;
   f.px = fmaf(t, r.dx, r.ox);
   f.py = fmaf(t, r.dy, r.oy);
@@ -717,6 +863,13 @@ __device__ __forceinline__ Surface surface_at(const SceneDev& s, const Ray& r, f
     float4 g = ld4(s.pgeom, id - s.n_spheres);
     f.nx = g.x; f.ny = g.y; f.nz = g.z;
   }
+  f.ar = f.ag = f.ab = f.kr = f.shine = 0.0f;
+  return f;
+}
+
+// Surface point with its material.
+__device__ __forceinline__ Surface surface_at(const SceneDev& s, const Ray& r, float t, int id) {
+  Surface f = surface_geom(s, r, t, id);
   float4 m = ld4(s.mat, id);
   f.ar = m.x; f.ag = m.y; f.ab = m.z; f.kr = m.w;
   f.shine = ld1(s.shine, id);
@@ -744,12 +897,13 @@ __device__ __forceinline__ float spec_base(int model, float nx, float ny, float 
 // over lights with n.l > 0 and no occluder; returns the lit-light mask.
 // Only lanes with `on` take part (the others get a mask of 0); the shadow
 // rays of a light are traced while any lane of the wave needs one.
-template <bool kPrefilter = true, class Cnt = NoCount>
+template <bool kPrefilter = true, bool kDense = false, class Cnt = NoCount>
 __device__ __forceinline__ uint32_t light_terms(const SceneDev& s, const Surface& f, const Ray& r,
                                                 bool on, float& A, float& S, Cnt& cnt) {
   A = s.ambient;
   S = 0.0f;
   uint32_t lit = 0;
+  const float shine = ld1(s.shine, f.id);
   for (int l = 0; l < s.n_lights; ++l) {
     float4 q = ld4(s.light, l);
     float lx = q.x - f.px, ly = q.y - f.py, lz = q.z - f.pz;
@@ -763,12 +917,12 @@ __device__ __forceinline__ uint32_t light_terms(const SceneDev& s, const Surface
     const bool act = on && nl > 0.0f;
     if (wave_any(act)) {
       if (act) cnt.ray(kCntShadow);
-      const bool occ = occluded<kPrefilter>(s, l, q, f, lx, ly, lz, dist, act, cnt);
+      const bool occ = occluded<kPrefilter, kDense>(s, l, q, f, lx, ly, lz, dist, act, cnt);
       if (act && !occ) {
         lit |= 1u << l;
         A = fmaf(q.w, nl, A);
         float x = spec_base(s.spec_model, f.nx, f.ny, f.nz, lx, ly, lz, -r.dx, -r.dy, -r.dz, nl);
-        S = fmaf(q.w * s.spec_strength, spec_pow(x, f.shine), S);
+        S = fmaf(q.w * s.spec_strength, spec_pow(x, shine), S);
       }
     }
   }
@@ -833,9 +987,11 @@ __device__ __forceinline__ int trace_segment(const SceneDev& s, PathState& ps, i
   alive = hit && k < depth;
   if (wave_any(hit)) {
     // lanes without a hit shade primitive 0 along and keep nothing of it
-    Surface f = surface_at(s, ps.r, t, hit ? id : 0);
+    Surface f = surface_geom(s, ps.r, t, hit ? id : 0);
     float A, S;
-    const uint32_t lit = light_terms<kPrefilter>(s, f, ps.r, hit, A, S, cnt);
+    const uint32_t lit = light_terms<kPrefilter, kFromEye>(s, f, ps.r, hit, A, S, cnt);
+    const float4 mat = ld4(s.mat, f.id);
+    f.ar = mat.x; f.ag = mat.y; f.ab = mat.z; f.kr = mat.w;
     if (hit) {
       sink.lit(k, lit);
       if (k < depth) {
