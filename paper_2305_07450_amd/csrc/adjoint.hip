@@ -18,6 +18,8 @@
 // sphere id with a fixed xor butterfly and adds them into its own LDS
 // accumulator; each workgroup then writes one partial vector, and a second
 // kernel adds the partials in a fixed order.  No floating-point atomics.
+#include <type_traits>
+
 #include "rt_internal.hpp"
 
 namespace rtk {
@@ -100,7 +102,9 @@ struct V3 {
 
 __device__ __forceinline__ float dotv(V3 a, V3 b) { return dot3(a.x, a.y, a.z, b.x, b.y, b.z); }
 
-template <bool kHasRecords>
+// kL: lights the per-lane light accumulators are sized for (a bound on the
+// scene's light count, so that a 1-light scene does not hold registers for 8).
+template <bool kHasRecords, int kL>
 __global__ __launch_bounds__(256) void adjoint_kernel(SceneDev s, CameraDev c, int depth,
                                                        const float* __restrict__ grad_rgb,
                                                        const int32_t* __restrict__ rec_ids,
@@ -117,9 +121,9 @@ __global__ __launch_bounds__(256) void adjoint_kernel(SceneDev s, CameraDev c, i
   for (int i = threadIdx.x; i < waves * per_wave; i += blockDim.x) acc[i] = 0.0f;
   __syncthreads();
 
-  float qbar[kMaxLights][3];
-  float ibar[kMaxLights];
-  for (int l = 0; l < kMaxLights; ++l) {
+  float qbar[kL][3];
+  float ibar[kL];
+  for (int l = 0; l < kL; ++l) {
     qbar[l][0] = qbar[l][1] = qbar[l][2] = 0.0f;
     ibar[l] = 0.0f;
   }
@@ -225,9 +229,10 @@ __global__ __launch_bounds__(256) void adjoint_kernel(SceneDev s, CameraDev c, i
           V3 n = {f.nx, f.ny, f.nz}, d = {r.dx, r.dy, r.dz};
           V3 nbar = {0.f, 0.f, 0.f}, pbar = {0.f, 0.f, 0.f};
           V3 dloc = {0.f, 0.f, 0.f};  // adjoint of d through the view vector
-          // light terms
-          for (int l = 0; l < L; ++l) {
-            if (!((rr.lits[k] >> l) & 1u)) continue;
+          // light terms (unrolled over kL so the accumulators stay in registers)
+#pragma unroll
+          for (int l = 0; l < kL; ++l) {
+            if (l >= L || !((rr.lits[k] >> l) & 1u)) continue;
             float4 q = ld4(s.light, l);
             V3 lv = {q.x - f.px, q.y - f.py, q.z - f.pz};
             float d2 = dotv(lv, lv);
@@ -324,7 +329,7 @@ __global__ __launch_bounds__(256) void adjoint_kernel(SceneDev s, CameraDev c, i
         uint64_t pending = __ballot(sid >= 0);
         while (pending) {
           const int leader = __builtin_ctzll(pending);
-          const int key = __shfl(sid, leader, 64);
+          const int key = __builtin_amdgcn_readlane(sid, leader);
           const bool mine = sid == key;
           float v[7] = {sa0, sa1, sa2, skr, sc0, sc1, sc2};
 #pragma unroll
@@ -340,7 +345,9 @@ __global__ __launch_bounds__(256) void adjoint_kernel(SceneDev s, CameraDev c, i
   // light gradients: wave butterfly, then one LDS slot per wave
   __syncthreads();
   float* lacc = acc + waves * per_wave;
-  for (int l = 0; l < L; ++l) {
+#pragma unroll
+  for (int l = 0; l < kL; ++l) {
+    if (l >= L) break;
     float v[4] = {qbar[l][0], qbar[l][1], qbar[l][2], ibar[l]};
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -424,14 +431,17 @@ hipError_t launch_backward(const rt_scene_s& sc, const CameraDev& c, int depth,
   int blocks = adjoint_blocks(sc.grad_stride);
   if (blocks > n_tiles) blocks = n_tiles;
   SceneDev s = sc.view();
-  if (rec_ids)
-    hipLaunchKernelGGL(adjoint_kernel<true>, dim3(blocks), dim3(64 * waves), lds, stream, s, c,
-                       depth, grad_rgb, rec_ids, rec_lit, sc.partials, sc.grad_stride, n_tiles_x,
-                       n_tiles);
-  else
-    hipLaunchKernelGGL(adjoint_kernel<false>, dim3(blocks), dim3(64 * waves), lds, stream, s, c,
-                       depth, grad_rgb, rec_ids, rec_lit, sc.partials, sc.grad_stride, n_tiles_x,
-                       n_tiles);
+  // the smallest light bucket that holds the scene's lights
+  auto pick = [&](auto with_records) {
+    constexpr bool kRec = decltype(with_records)::value;
+    if (L <= 1) return adjoint_kernel<kRec, 1>;
+    if (L <= 2) return adjoint_kernel<kRec, 2>;
+    if (L <= 4) return adjoint_kernel<kRec, 4>;
+    return adjoint_kernel<kRec, kMaxLights>;
+  };
+  auto kern = rec_ids ? pick(std::true_type{}) : pick(std::false_type{});
+  hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * waves), lds, stream, s, c, depth, grad_rgb,
+                     rec_ids, rec_lit, sc.partials, sc.grad_stride, n_tiles_x, n_tiles);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int total = 7 * N + 4 * L;
