@@ -162,6 +162,43 @@ def bench_batch(rt, scenegen, stream, steps):
             "create_s": round(create_s, 3)}
 
 
+def bench_configs(rt, scenegen, stream, indices=(0, 2), reps=20):
+    """The other single-image workloads (the small 256x144 scene and 4K with 512
+    spheres): frame time, frames/s, primary Mrays/s and the algorithmic FP32
+    rate, measured like the headline."""
+    out = {}
+    for i in indices:
+        wl = scenegen.make_workload(i)
+        W, H, D = wl.W, wl.H, wl.depth
+        h = rt.SceneHandle(wl.scene)
+        rgb = torch_empty_image(H, W)
+        counts = rt.render_counts(h.handle, wl.camera, W, H, D)
+        ms = time_gpu(lambda: rt.rt_render(h.handle, wl.camera, W, H, D, rgb, None, None, stream),
+                      reps, 3, stream)
+        flops = FLOP_SPHERE_TEST * counts["sphere_tests"] + FLOP_PLANE_TEST * counts["plane_tests"]
+        out[wl.name] = {"ms": round(ms, 4), "fps": round(1e3 / ms, 1),
+                        "primary_mrays_per_s": round(W * H / (ms * 1e-3) / 1e6, 1),
+                        "tflops_algorithmic": round(flops / (ms * 1e-3) / 1e12, 2),
+                        "frac_of_peak": round(flops / (ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, 4)}
+        h.close()
+    return out
+
+
+def torch_empty_image(H, W):
+    import torch
+    return torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
+
+
+# The paper's own frame rates for its render method (one light, one plane, five
+# spheres and a skybox, one bounce, GUI-inclusive timing, on the NVIDIA GeForce
+# RTX 2060 through TornadoVM/OpenCL).  Context only: another machine, another
+# scene and another timing.
+PAPER_CONTEXT = {"fps_1280x720": 234, "fps_1920x1080": 152, "fps_3840x2160": 45,
+                 "hardware": "NVIDIA GeForce RTX 2060 (TornadoVM, OpenCL backend)",
+                 "scene": "1 light, 1 plane, 5 spheres, skybox, 1 bounce, GUI-inclusive",
+                 "use": "context only"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -256,6 +293,8 @@ def main():
     if not args.no_extras:
         out["fwd_bwd"] = bench_fwd_bwd(rt, scenegen, stream, 20)
         out["batch"] = bench_batch(rt, scenegen, stream, 10)
+        out["other_workloads"] = bench_configs(rt, scenegen, stream)
+        out["paper_context"] = PAPER_CONTEXT
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(out), flush=True)

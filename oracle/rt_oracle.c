@@ -25,6 +25,13 @@
  *     and S = sum over lit lights of I k_s spec (white lights, no falloff);
  *   - a light with n.L <= 0 gets no diffuse, no specular and no shadow ray;
  *   - occluded iff some primitive has a root in (t_min, |q - p|);
+ *   - soft shadows (Section 3.6.1): the light's sample points lie on the disk
+ *     about q perpendicular to the direction from p, at radius 2 R sqrt(i/n)
+ *     and angle i times the golden angle, as printed; the disk's in-plane
+ *     orientation, which the paper does not fix, follows Duff et al. (2017);
+ *     "blocked / total" is read as the share of light removed, so diffuse
+ *     and specular are scaled by the unblocked share; a sample behind the
+ *     tangent plane at p is blocked; the shading direction is the centre's;
  *   - the view vector on every bounce is minus the incoming ray direction;
  *   - a miss returns the background colour (black by default).
  */
@@ -170,6 +177,54 @@ static int in_cast_shadow(const or_scene* s, const double p[3], const double l[3
   return 0;
 }
 
+/* ---- Section 3.6.1: soft shadows ---------------------------------------- */
+
+/* An orthonormal pair (b1, b2) spanning the plane perpendicular to the unit
+ * vector w, by the branchless construction of Duff et al., "Building an
+ * Orthonormal Basis, Revisited" (JCGT 6(1), 2017). */
+static void perp_basis(const double w[3], double b1[3], double b2[3]) {
+  double sign = copysign(1.0, w[2]);
+  double a = -1.0 / (sign + w[2]);
+  double b = w[0] * w[1] * a;
+  b1[0] = 1.0 + sign * w[0] * w[0] * a;
+  b1[1] = sign * b;
+  b1[2] = -sign * w[0];
+  b2[0] = b;
+  b2[1] = sign + w[1] * w[1] * a;
+  b2[2] = -w[1];
+}
+
+/* Fraction of the light's sample points visible from p.  The light is a
+ * sphere of radius R about q; its great circle facing p is the disk about q
+ * perpendicular to w = (q - p)/|q - p|.  Point i of n follows the sunflower
+ * arrangement (Vogel): radius 2 R sqrt(i/n) and angle i * phi, phi the golden
+ * angle pi (3 - sqrt 5), measured from b1 towards b2.  A point's shadow ray
+ * from p is blocked when it points into the surface (n.d <= 0: the point lies
+ * behind the tangent plane at p) or when some primitive has a root in
+ * (t_min, |s - p|); the fraction is unblocked / n. */
+static double soft_visibility(const or_scene* s, const double p[3], const double n[3],
+                              const double q[3], const double w[3], int64_t* tests) {
+  const int32_t ns = s->shadow_samples;
+  const double phi = OR_PI * (3.0 - sqrt(5.0));
+  double b1[3], b2[3];
+  perp_basis(w, b1, b2);
+  int32_t visible = 0;
+  for (int32_t i = 0; i < ns; ++i) {
+    double r = 2.0 * s->light_radius * sqrt((double)i / (double)ns);
+    double th = (double)i * phi;
+    double c = cos(th), sn = sin(th);
+    double pt[3], d[3];
+    for (int k = 0; k < 3; ++k) pt[k] = q[k] + r * (c * b1[k] + sn * b2[k]);
+    for (int k = 0; k < 3; ++k) d[k] = pt[k] - p[k];
+    double dist = sqrt(dot3(d, d));
+    for (int k = 0; k < 3; ++k) d[k] /= dist;
+    if (!(dot3(n, d) > 0.0)) continue;
+    if (tests) tests[OR_CNT_SHADOW_RAYS] += 1;
+    if (!in_cast_shadow(s, p, d, dist, tests)) ++visible;
+  }
+  return (double)visible / (double)ns;
+}
+
 /* ---- Section 3.5: Phong / Blinn-Phong local illumination ---------------- */
 
 /* Light terms at a hit point: A (multiplies the surface colour) and S (added,
@@ -192,10 +247,19 @@ static uint32_t light_terms(const or_scene* s, const double p[3], const double n
     ld[2] /= dist;
     double nl = dot3(n, ld);
     if (!(nl > 0.0)) continue;
-    if (tests) tests[OR_CNT_SHADOW_RAYS] += 1;
-    if (in_cast_shadow(s, p, ld, dist, tests)) continue;
+    /* the share of the light that reaches p: 0 or 1 for a point light, the
+     * visible fraction of the samples for an area light (Section 3.6.1) */
+    double vis;
+    if (s->shadow_samples > 1) {
+      vis = soft_visibility(s, p, n, q, ld, tests);
+      if (!(vis > 0.0)) continue;
+    } else {
+      if (tests) tests[OR_CNT_SHADOW_RAYS] += 1;
+      if (in_cast_shadow(s, p, ld, dist, tests)) continue;
+      vis = 1.0;
+    }
     lit |= 1u << l;
-    double intensity = q[3];
+    double intensity = q[3] * vis;
     *A += intensity * nl;
     double x;
     if (s->spec_model == OR_SPEC_PHONG) {

@@ -47,6 +47,11 @@ typedef struct {
   const double* light;         /* [L][4] position, intensity            */
   double ambient, spec_strength, t_min;
   double background[3];
+  /* Soft shadows (Section 3.6.1): with shadow_samples > 1 every light is a
+   * sphere of radius light_radius sampled at shadow_samples points of its
+   * great circle facing the hit point; 0 or 1 sample: hard shadows. */
+  int32_t shadow_samples;
+  double light_radius;
 } or_scene;
 
 typedef struct {
@@ -60,7 +65,8 @@ typedef struct {
   double* rgb;        /* [n][3] linear colour                                 */
   int32_t* prim_id;   /* [n]    primary-segment hit id, OR_MISS on a miss     */
   int32_t* seg_id;    /* [n][depth+1] hit id per segment                      */
-  uint32_t* lit;      /* [n][depth+1] bit l: light l lit the hit (n.L>0, no occluder) */
+  uint32_t* lit;      /* [n][depth+1] bit l: light l lit the hit (n.L>0 and no
+                         occluder; with soft shadows: some sample unblocked)  */
   double* margin;     /* [n]    decision margin of the primary segment        */
   int64_t* counts;    /* [OR_NCOUNTS] summed over the requested pixels        */
 } or_outputs;
