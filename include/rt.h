@@ -44,6 +44,7 @@ extern "C" {
 #define RT_MAX_PLANES 16
 #define RT_MAX_DIM 16384      /* largest W or H                                 */
 #define RT_MAX_BATCH 4096     /* largest number of scenes in one batch          */
+#define RT_MAX_SAMPLES 4096   /* most shadow samples per light (rt_render_soft)  */
 
 typedef enum {
   RT_OK = 0,
@@ -161,6 +162,28 @@ rt_status rt_render(rt_scene scene, const rt_camera* cam, int32_t W, int32_t H, 
 rt_status rt_render_ex(rt_scene scene, const rt_camera* cam, int32_t W, int32_t H, int32_t depth,
                        float* rgb_out, int32_t* id_out, const rt_records* rec, uint32_t flags,
                        void* stream);
+
+/* Render one image with soft shadows (the paper's soft cast shadows, Section
+ * 3.6.1): every light is a sphere of radius light_radius about its position,
+ * sampled at `samples` points of its great circle facing the hit point in the
+ * sunflower arrangement (point i at radius 2 light_radius sqrt(i/samples) and
+ * angle i times the golden angle pi (3 - sqrt 5), in the plane perpendicular
+ * to the direction from the hit point to the light; the in-plane orientation
+ * follows Duff et al., "Building an Orthonormal Basis, Revisited", 2017).  A
+ * sample's shadow ray is blocked when the sample lies behind the tangent plane
+ * at the hit point or a primitive has a root between t_min and the sample;
+ * diffuse and specular of that light are scaled by the unblocked share.
+ *   samples       1 .. RT_MAX_SAMPLES; samples == 1 or light_radius == 0 is
+ *                 the point light, rendered exactly as rt_render_ex;
+ *   light_radius  finite, >= 0, scene units;
+ *   rgb_out, id_out, flags as rt_render_ex.  No records: the adjoint and the
+ *   batched launch take point lights.
+ * Launches two kernels (the sample table, then the render); no allocation,
+ * capture-safe.  Renders of one scene must not overlap in time (the sample
+ * table and the eye cones live in the scene's buffer). */
+rt_status rt_render_soft(rt_scene scene, const rt_camera* cam, int32_t W, int32_t H,
+                         int32_t depth, int32_t samples, float light_radius, float* rgb_out,
+                         int32_t* id_out, uint32_t flags, void* stream);
 
 /* Work counters of the render of one image, as the method defines its work
  * (Sections 3.4.1 and 3.6: every segment tests every primitive; a shadow ray

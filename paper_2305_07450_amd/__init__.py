@@ -27,6 +27,7 @@ RT_MAX_LIGHTS = 8
 RT_MAX_SPHERES = 4096
 RT_MAX_PLANES = 16
 RT_RENDER_NO_PREFILTER = 1
+RT_MAX_SAMPLES = 4096
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(
@@ -76,6 +77,8 @@ _sig = {
                             C.POINTER(rt_records), _vp]),
     "rt_render_ex": (C.c_int, [_vp, C.POINTER(rt_camera), _i32, _i32, _i32, _vp, _vp,
                                C.POINTER(rt_records), C.c_uint32, _vp]),
+    "rt_render_soft": (C.c_int, [_vp, C.POINTER(rt_camera), _i32, _i32, _i32, _i32, C.c_float,
+                                 _vp, _vp, C.c_uint32, _vp]),
     "rt_render_counts": (C.c_int, [_vp, C.POINTER(rt_camera), _i32, _i32, _i32, _vp, _vp]),
     "rt_render_backward": (C.c_int, [_vp, C.POINTER(rt_camera), _i32, _i32, _i32, _vp,
                                      C.POINTER(rt_records), C.POINTER(rt_grads), _vp]),
@@ -215,6 +218,17 @@ def rt_render_ex(handle: int, camera, W: int, H: int, depth: int, rgb_out: torch
 
 
 COUNT_NAMES = ("sphere_tests", "plane_tests", "primary_rays", "reflection_rays", "shadow_rays")
+
+
+def rt_render_soft(handle: int, camera, W: int, H: int, depth: int, samples: int,
+                   light_radius: float, rgb_out: torch.Tensor,
+                   id_out: Optional[torch.Tensor] = None, flags: int = 0, stream=None):
+    """Soft shadows: every light a sphere of radius light_radius sampled at
+    `samples` points (see include/rt.h)."""
+    cam = make_camera(camera)
+    _check(_lib.rt_render_soft(handle, C.byref(cam), W, H, depth, int(samples),
+                               float(light_radius), _ptr(rgb_out), _ptr(id_out), int(flags),
+                               _stream(stream)))
 
 
 def rt_render_counts(handle: int, camera, W: int, H: int, depth: int, counts: torch.Tensor,

@@ -66,6 +66,64 @@ __global__ __launch_bounds__(256) void render_kernel(SceneDev s, CameraDev c, in
   }
 }
 
+// Soft-shadow render: the same paths with every light sampled (SoftShadows).
+template <bool kPrefilter>
+__global__ __launch_bounds__(256) void render_soft_kernel(SceneDev s, CameraDev c, int depth,
+                                                           SoftShadows sh,
+                                                           float* __restrict__ rgb,
+                                                           int32_t* __restrict__ id_out) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int x = blockIdx.x * kBlock + (wave & 1) * kTile + (lane & 7);
+  const int y = blockIdx.y * kBlock + (wave >> 1) * kTile + (lane >> 3);
+  const bool live = x < c.W && y < c.H;
+  if (!wave_any(live)) return;
+  const int64_t pix = live ? (int64_t)y * c.W + x : 0;
+  Ray r = primary_ray(c, live ? x : c.W - 1, live ? y : c.H - 1);
+  float cr, cg, cb;
+  int prim;
+  NoRecords sink;
+  trace_path<NoRecords, NoCount, kPrefilter, SoftShadows>(s, r, depth, live, cr, cg, cb, prim,
+                                                          sink, NoCount(), sh);
+  if (live) {
+    rgb[3 * pix + 0] = cr;
+    rgb[3 * pix + 1] = cg;
+    rgb[3 * pix + 2] = cb;
+    if (id_out) id_out[pix] = prim;
+  }
+}
+
+// Sample points of the sunflower arrangement in units of the light radius:
+// point i of n at radius 2 sqrt(i/n) and angle i times the golden angle
+// pi (3 - sqrt 5), as (x, y) in the disk basis; computed in double and
+// rounded once.
+__global__ void sample_table_kernel(int n, float2* __restrict__ table) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const double golden = 3.14159265358979323846 * (3.0 - sqrt(5.0));
+    const double r = 2.0 * sqrt((double)i / (double)n);
+    const double th = (double)i * golden;
+    table[i] = make_float2((float)(r * cos(th)), (float)(r * sin(th)));
+  }
+}
+
+hipError_t launch_render_soft(const rt_scene_s& sc, const CameraDev& c, int depth, int samples,
+                              float radius, float* rgb, int32_t* ids, bool prefilter,
+                              hipStream_t stream) {
+  hipLaunchKernelGGL(sample_table_kernel, dim3((samples + 255) / 256), dim3(256), 0, stream,
+                     samples, sc.soft_table);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  SoftShadows sh;
+  sh.n = samples;
+  sh.radius = radius;
+  sh.table = sc.soft_table;
+  dim3 grid((c.W + kBlock - 1) / kBlock, (c.H + kBlock - 1) / kBlock);
+  auto kern = prefilter ? render_soft_kernel<true> : render_soft_kernel<false>;
+  hipLaunchKernelGGL(kern, grid, dim3(256), 0, stream, sc.view(), c, depth, sh, rgb, ids);
+  return hipGetLastError();
+}
+
 // Counting launch: the same paths, plus the algorithmic counters summed per
 // wave (xor butterfly) and added to counts[kNumCounts] with integer atomics.
 __global__ __launch_bounds__(256) void count_kernel(SceneDev s, CameraDev c, int depth,

@@ -9,6 +9,8 @@
 #include <mutex>
 #include <new>
 
+#include <cmath>
+
 #include "rt_internal.hpp"
 
 namespace rtk {
@@ -240,6 +242,7 @@ rt_status rt_scene_upload(const rt_scene_desc* d, void* stream, rt_scene* out) {
   sc->staging_floats = 9 * N + 9 * P + 4 * L;
   size_t o_stage = take(sc->staging_floats * sizeof(float));
   size_t o_part = take((size_t)blocks * sc->grad_stride * sizeof(float));
+  size_t o_soft = take((size_t)RT_MAX_SAMPLES * sizeof(float2));
   sc->bytes = off;
   hipError_t e = hipGetDevice(&sc->device);
   if (e == hipSuccess) e = hipMalloc(&sc->buffer, sc->bytes);
@@ -258,6 +261,7 @@ rt_status rt_scene_upload(const rt_scene_desc* d, void* stream, rt_scene* out) {
   sc->light_cone = (float4*)(base + o_light_cone);
   sc->staging = (float*)(base + o_stage);
   sc->partials = (float*)(base + o_part);
+  sc->soft_table = (float2*)(base + o_soft);
   st = upload_values(sc, d, (hipStream_t)stream);
   if (st != RT_OK) {
     (void)hipFree(sc->buffer);
@@ -321,6 +325,29 @@ rt_status rt_render_ex(rt_scene sc, const rt_camera* cam, int32_t W, int32_t H, 
                       rec ? rec->lit : nullptr, !(flags & RT_RENDER_NO_PREFILTER),
                       (hipStream_t)stream);
   return hip_fail(e, "render launch");
+}
+
+rt_status rt_render_soft(rt_scene sc, const rt_camera* cam, int32_t W, int32_t H,
+                         int32_t depth, int32_t samples, float light_radius, float* rgb_out,
+                         int32_t* id_out, uint32_t flags, void* stream) {
+  if (!sc) return fail(RT_ERR_INVALID_ARG, "scene is NULL");
+  if (samples < 1 || samples > RT_MAX_SAMPLES)
+    return fail(RT_ERR_INVALID_ARG, "samples %d outside [1, %d]", samples, RT_MAX_SAMPLES);
+  if (!(light_radius >= 0.0f) || !std::isfinite(light_radius))
+    return fail(RT_ERR_INVALID_ARG, "light_radius must be finite and >= 0");
+  if (samples == 1 || light_radius == 0.0f)   // the point light
+    return rt_render_ex(sc, cam, W, H, depth, rgb_out, id_out, nullptr, flags, stream);
+  if (flags & ~(uint32_t)RT_RENDER_NO_PREFILTER)
+    return fail(RT_ERR_INVALID_ARG, "unknown render flags 0x%x", flags);
+  rt_status st = validate_camera(cam, W, H, depth);
+  if (st != RT_OK) return st;
+  if (!rgb_out) return fail(RT_ERR_INVALID_ARG, "rgb_out is NULL");
+  CameraDev c = camera_dev(*cam, W, H);
+  hipError_t e = launch_eye_cones(*sc, c, (hipStream_t)stream);
+  if (e == hipSuccess)
+    e = launch_render_soft(*sc, c, depth, samples, light_radius, rgb_out, id_out,
+                           !(flags & RT_RENDER_NO_PREFILTER), (hipStream_t)stream);
+  return hip_fail(e, "soft render launch");
 }
 
 rt_status rt_render_counts(rt_scene sc, const rt_camera* cam, int32_t W, int32_t H,

@@ -29,6 +29,7 @@ struct rt_scene_s {
   float4* light_cone = nullptr;  // [L*n4 + kGroup]  rows of n4, rebuilt by every upload/update
   float* staging = nullptr;     // raw copy of host desc arrays
   size_t staging_floats = 0;
+  float2* soft_table = nullptr; // [RT_MAX_SAMPLES] shadow sample points of the last soft render
   float* partials = nullptr;    // adjoint partials [kAdjointBlocks][grad_stride]
   int grad_stride = 0;          // 7N + 4L (padded)
 
@@ -69,6 +70,9 @@ hipError_t launch_pack(const rt_scene_s& sc, const RawScene& raw, hipStream_t st
 
 // Cones of every sphere seen from the camera's eye, into sc.eye_cone.
 hipError_t launch_eye_cones(const rt_scene_s& sc, const CameraDev& c, hipStream_t stream);
+hipError_t launch_render_soft(const rt_scene_s& sc, const CameraDev& c, int depth, int samples,
+                              float radius, float* rgb, int32_t* ids, bool prefilter,
+                              hipStream_t stream);
 
 hipError_t launch_render(const SceneDev& s, const CameraDev& c, int depth, float* rgb,
                          int32_t* ids, int32_t* rec_ids, uint8_t* rec_lit, bool prefilter,

@@ -431,12 +431,33 @@ struct WaveBundle {
   float ex, ey, ez;   // axis
   float c, s;         // cos(phi), sin(phi)
   float reach;        // rho / sin(phi) + rho: farthest origin from the apex
+  float mx, my, mz;   // centre of the ball of origins
+  float rho;          // its radius
   bool full;          // all lanes executing and some participate
   bool on;            // full, and phi below 60 degrees
 };
 
 // Widest bundle still worth its cost (cos of the half-angle).
 constexpr float kBundleMinCos = 0.5f;
+
+// Cone half-angle phi = acos(c) for a bundle whose ball is set: the apex
+// rho / sin(phi) behind the ball's centre; on when phi is below 60 degrees.
+__device__ __forceinline__ void bundle_apex(WaveBundle& b, float c) {
+  // decided on phi itself: sin(phi) is also small when phi is near 180 degrees
+  b.on = b.full && c > kBundleMinCos;
+  float sn = fsqrt(fmaxf(fmaf(-c, c, 1.0f), 0.0f));
+  if (sn < 1e-3f) {   // phi near 0 (c > kBundleMinCos > 0 when on)
+    sn = 1e-3f;
+    c = 0.9999995f;   // below sqrt(1 - 1e-6)
+  }
+  b.c = c;
+  b.s = sn;
+  const float back = b.rho / sn;
+  b.vx = fmaf(-b.ex, back, b.mx);
+  b.vy = fmaf(-b.ey, back, b.my);
+  b.vz = fmaf(-b.ez, back, b.mz);
+  b.reach = back + b.rho;
+}
 
 __device__ __forceinline__ WaveBundle wave_bundle(bool take, const Ray& r) {
   WaveBundle b;
@@ -447,6 +468,7 @@ __device__ __forceinline__ WaveBundle wave_bundle(bool take, const Ray& r) {
   b.c = -1.0f;
   b.s = 0.0f;
   b.reach = 0.0f;
+  b.mx = b.my = b.mz = b.rho = 0.0f;
   if (b.on) {
     const int f = (int)__builtin_ctzll(m);
     float mx = lane_read(r.ox, f), my = lane_read(r.oy, f), mz = lane_read(r.oz, f);
@@ -467,21 +489,9 @@ __device__ __forceinline__ WaveBundle wave_bundle(bool take, const Ray& r) {
       rho2 = wave_min(take ? -dot3(qx, qy, qz, qx, qy, qz) : 0.0f);
     }
     const float rho = fmaf(fsqrt(-rho2), 1.00001f, 1e-6f);
-    float c = refined_axis(take, r.dx, r.dy, r.dz, b.ex, b.ey, b.ez) - 2e-6f;
-    // decided on phi itself: sin(phi) is also small when phi is near 180 degrees
-    b.on = c > kBundleMinCos;
-    float sn = fsqrt(fmaxf(fmaf(-c, c, 1.0f), 0.0f));
-    if (sn < 1e-3f) {   // phi near 0 (c > kBundleMinCos > 0 here)
-      sn = 1e-3f;
-      c = 0.9999995f;   // below sqrt(1 - 1e-6)
-    }
-    b.c = c;
-    b.s = sn;
-    const float back = rho / sn;
-    b.vx = fmaf(-b.ex, back, mx);
-    b.vy = fmaf(-b.ey, back, my);
-    b.vz = fmaf(-b.ez, back, mz);
-    b.reach = back + rho;
+    b.mx = mx; b.my = my; b.mz = mz;
+    b.rho = rho;
+    bundle_apex(b, refined_axis(take, r.dx, r.dy, r.dz, b.ex, b.ey, b.ez) - 2e-6f);
   }
   return b;
 }
@@ -893,13 +903,155 @@ __device__ __forceinline__ float spec_base(int model, float nx, float ny, float 
   return hl2 > 0.0f ? dot3(nx, ny, nz, hx, hy, hz) * frsq(hl2) : 0.0f;
 }
 
+// ---- Soft shadows (Section 3.6.1) -------------------------------------------
+// Shadow policies of the path code: point lights (one shadow ray per lit
+// light), or spherical lights of radius R sampled at n points of their great
+// circle facing the hit point.
+struct HardShadows {
+  static constexpr bool kSoft = false;
+};
+struct SoftShadows {
+  static constexpr bool kSoft = true;
+  int n;                // samples per light
+  float radius;         // light radius R
+  const float2* table;  // [n]: sample i in units of R in the disk basis,
+                        // 2 sqrt(i/n) (cos(i phi), sin(i phi)), phi the golden angle
+};
+
+// Chunks of 64 spheres whose candidate masks a soft-shadow bound keeps; a
+// scene with more spheres tests every sphere for every sample.
+constexpr int kSoftChunks = 4;
+
+// An orthonormal pair perpendicular to the unit w (Duff et al., "Building an
+// Orthonormal Basis, Revisited", JCGT 2017).
+__device__ __forceinline__ void perp_basis(float wx, float wy, float wz, float& ax, float& ay,
+                                           float& az, float& bx, float& by, float& bz) {
+  const float sign = copysignf(1.0f, wz);
+  const float a = -__builtin_amdgcn_rcpf(sign + wz);
+  const float b = wx * wy * a;
+  ax = fmaf(sign * wx * wx, a, 1.0f);
+  ay = sign * b;
+  az = -sign * wx;
+  bx = b;
+  by = fmaf(wy * wy, a, sign);
+  bz = -wy;
+}
+
+// Exact test of one sphere against the sample rays of the lanes not yet
+// blocked: a root in (t_min, dist) of a sphere other than the surface.
+__device__ __forceinline__ void soft_blocker(float4 g, int i, const Ray& sr, float dist, float tmin,
+                                             int self, bool& blk) {
+  float b;
+  const float ff = sphere_ff(g, sr, b);
+  const bool in = !blk & (ff <= g.w) & (i != self);
+  if (wave_any(in)) {
+    const float sq = fsqrt(in ? g.w - ff : 0.0f);
+    const float t0 = -b - sq, t1 = -b + sq;
+    blk = blk || (in && ((t0 > tmin && t0 < dist) || (t1 > tmin && t1 < dist)));
+  }
+}
+
+// Share of light l's sample points whose shadow rays from the hit point p
+// reach the light, for the lanes with `act` (0 for the others).  The points
+// lie on the disk of radius 2R about the light centre q perpendicular to the
+// unit direction w from p to q (the light's great circle facing p), at
+// q + R (a_i e1 + b_i e2) with (e1, e2) from perp_basis(w).  A sample behind
+// the tangent plane at p (n.d <= 0) is blocked; otherwise its ray is blocked
+// when a primitive other than the surface itself (which the ray leaves
+// outwards) has a root in (t_min, |s - p|).
+//
+// Spheres are bounded once for all samples of the wave: every sample ray
+// starts at a lane's p and points within alpha = atan(2R / |q - p|) of that
+// lane's w, so the wave bundle of the hit points and light directions, with
+// its cone widened by the largest alpha (less 2e-6 in cos for rounding), holds
+// every sample ray, and only the spheres it may meet are tested.
+template <bool kPrefilter>
+__device__ __forceinline__ float soft_visibility(const SceneDev& s, float4 q, const Surface& f,
+                                                 float lx, float ly, float lz, float dist,
+                                                 bool act, const SoftShadows& sh) {
+  float ax, ay, az, bx, by, bz;
+  perp_basis(lx, ly, lz, ax, ay, az, bx, by, bz);
+  const int self = f.id;
+  const float tmin = s.t_min;
+  uint64_t cand[kSoftChunks];
+#pragma unroll
+  for (int c = 0; c < kSoftChunks; ++c) cand[c] = 0;
+  bool culled = false;
+  if (kPrefilter && s.n_spheres <= 64 * kSoftChunks) {
+    Ray cr;
+    cr.ox = f.px; cr.oy = f.py; cr.oz = f.pz;
+    cr.dx = lx; cr.dy = ly; cr.dz = lz;
+    WaveBundle wb = wave_bundle(act, cr);
+    if (wb.full && wb.c > kBundleMinCos) {
+      // widen phi by the largest disk angle: cos(phi + alpha) from the cosines
+      const float two_r = 2.0f * sh.radius;
+      const float h = fsqrt(fmaf(dist, dist, two_r * two_r));
+      const float ca = wave_min(act ? dist * __builtin_amdgcn_rcpf(h) : 2.0f) - 2e-6f;
+      const float sa = fsqrt(fmaxf(fmaf(-ca, ca, 1.0f), 0.0f));
+      bundle_apex(wb, fmaf(wb.c, ca, -(wb.s * sa)) - 2e-6f);
+      if (wb.on) {
+        const int lane = __lane_id();
+#pragma unroll
+        for (int c = 0; c < kSoftChunks; ++c) {
+          if (64 * c < s.n_spheres) {
+            const int j = 64 * c + lane;
+            const int jc = j < s.n_spheres ? j : s.n_spheres - 1;
+            cand[c] = wave_mask((j < s.n_spheres) & sphere_may_meet(wb, s.geom[jc], s.rad[jc].x));
+          }
+        }
+        culled = true;
+      }
+    }
+  }
+  int visible = 0;
+  for (int i = 0; i < sh.n; ++i) {
+    const float2 t = ld2(sh.table, i);
+    const float u = sh.radius * t.x, v = sh.radius * t.y;
+    float dx = fmaf(u, ax, fmaf(v, bx, q.x)) - f.px;
+    float dy = fmaf(u, ay, fmaf(v, by, q.y)) - f.py;
+    float dz = fmaf(u, az, fmaf(v, bz, q.z)) - f.pz;
+    const float d2 = dot3(dx, dy, dz, dx, dy, dz);
+    const float inv = frsq(d2);
+    const float di = d2 * inv;
+    dx *= inv; dy *= inv; dz *= inv;
+    bool blk = !act || !(dot3(f.nx, f.ny, f.nz, dx, dy, dz) > 0.0f);
+    if (wave_any(!blk)) {
+      Ray sr;
+      sr.ox = f.px; sr.oy = f.py; sr.oz = f.pz;
+      sr.dx = dx; sr.dy = dy; sr.dz = dz;
+      if (culled) {
+#pragma unroll
+        for (int c = 0; c < kSoftChunks; ++c) {
+          uint64_t m = cand[c];
+          while (m) {
+            const int k = (int)__builtin_ctzll(m);
+            m &= m - 1;
+            soft_blocker(ld4(s.geom, 64 * c + k), 64 * c + k, sr, di, tmin, self, blk);
+            if (!wave_any(!blk)) m = 0;
+          }
+        }
+      } else {
+        scan_spheres(
+            s.geom, s.n4, [&](int j, float4 g) { soft_blocker(g, j, sr, di, tmin, self, blk); },
+            [&] { return !wave_any(!blk); });
+      }
+      for (int j = 0; j < s.n_planes; ++j)
+        blk = blk || (s.n_spheres + j != self && plane_root(ld4(s.pgeom, j), sr, tmin) < di);
+    }
+    visible += blk ? 0 : 1;
+  }
+  return act ? (float)visible / (float)sh.n : 0.0f;
+}
+
 // Light terms at a surface point: A = k_a + sum I (n.l), S = sum I k_s spec,
 // over lights with n.l > 0 and no occluder; returns the lit-light mask.
 // Only lanes with `on` take part (the others get a mask of 0); the shadow
 // rays of a light are traced while any lane of the wave needs one.
-template <bool kPrefilter = true, bool kDense = false, class Cnt = NoCount>
+template <bool kPrefilter = true, bool kDense = false, class Cnt = NoCount,
+          class Shadows = HardShadows>
 __device__ __forceinline__ uint32_t light_terms(const SceneDev& s, const Surface& f, const Ray& r,
-                                                bool on, float& A, float& S, Cnt& cnt) {
+                                                bool on, float& A, float& S, Cnt& cnt,
+                                                const Shadows& sh = Shadows()) {
   A = s.ambient;
   S = 0.0f;
   uint32_t lit = 0;
@@ -916,13 +1068,25 @@ __device__ __forceinline__ uint32_t light_terms(const SceneDev& s, const Surface
     float nl = dot3(f.nx, f.ny, f.nz, lx, ly, lz);
     const bool act = on && nl > 0.0f;
     if (wave_any(act)) {
-      if (act) cnt.ray(kCntShadow);
-      const bool occ = occluded<kPrefilter, kDense>(s, l, q, f, lx, ly, lz, dist, act, cnt);
-      if (act && !occ) {
-        lit |= 1u << l;
-        A = fmaf(q.w, nl, A);
-        float x = spec_base(s.spec_model, f.nx, f.ny, f.nz, lx, ly, lz, -r.dx, -r.dy, -r.dz, nl);
-        S = fmaf(q.w * s.spec_strength, spec_pow(x, shine), S);
+      if constexpr (Shadows::kSoft) {
+        // area light: scale by the share of sample rays that reach it
+        const float vis = soft_visibility<kPrefilter>(s, q, f, lx, ly, lz, dist, act, sh);
+        if (act && vis > 0.0f) {
+          lit |= 1u << l;
+          const float iv = q.w * vis;
+          A = fmaf(iv, nl, A);
+          float x = spec_base(s.spec_model, f.nx, f.ny, f.nz, lx, ly, lz, -r.dx, -r.dy, -r.dz, nl);
+          S = fmaf(iv * s.spec_strength, spec_pow(x, shine), S);
+        }
+      } else {
+        if (act) cnt.ray(kCntShadow);
+        const bool occ = occluded<kPrefilter, kDense>(s, l, q, f, lx, ly, lz, dist, act, cnt);
+        if (act && !occ) {
+          lit |= 1u << l;
+          A = fmaf(q.w, nl, A);
+          float x = spec_base(s.spec_model, f.nx, f.ny, f.nz, lx, ly, lz, -r.dx, -r.dy, -r.dz, nl);
+          S = fmaf(q.w * s.spec_strength, spec_pow(x, shine), S);
+        }
       }
     }
   }
@@ -964,9 +1128,10 @@ struct PathState {
 // `alive` says whether the path goes on (a hit below the bounce limit).
 // `sink.seg(k, id)` / `sink.lit(k, mask)` see the segment.  Every kernel runs
 // a segment through this one function, with all lanes of the wave executing.
-template <bool kFromEye, bool kPrefilter, class Sink, class Cnt>
+template <bool kFromEye, bool kPrefilter, class Sink, class Cnt, class Shadows = HardShadows>
 __device__ __forceinline__ int trace_segment(const SceneDev& s, PathState& ps, int k, int depth,
-                                             bool& alive, Sink& sink, Cnt& cnt) {
+                                             bool& alive, Sink& sink, Cnt& cnt,
+                                             const Shadows& sh = Shadows()) {
   float t;
   int id;
   if (kFromEye)
@@ -989,7 +1154,7 @@ __device__ __forceinline__ int trace_segment(const SceneDev& s, PathState& ps, i
     // lanes without a hit shade primitive 0 along and keep nothing of it
     Surface f = surface_geom(s, ps.r, t, hit ? id : 0);
     float A, S;
-    const uint32_t lit = light_terms<kPrefilter, kFromEye>(s, f, ps.r, hit, A, S, cnt);
+    const uint32_t lit = light_terms<kPrefilter, kFromEye>(s, f, ps.r, hit, A, S, cnt, sh);
     const float4 mat = ld4(s.mat, f.id);
     f.ar = mat.x; f.ag = mat.y; f.ab = mat.z; f.kr = mat.w;
     if (hit) {
@@ -1017,22 +1182,22 @@ __device__ __forceinline__ int trace_segment(const SceneDev& s, PathState& ps, i
 // executes the segment code together.  `sink.seg(k, id)` and
 // `sink.lit(k, mask)` see every traced segment; the caller marks untraced
 // segments.  Returns the number of segments traced (0 when not live).
-template <class Sink, class Cnt = NoCount, bool kPrefilter = true>
+template <class Sink, class Cnt = NoCount, bool kPrefilter = true, class Shadows = HardShadows>
 __device__ __forceinline__ int trace_path(const SceneDev& s, Ray r, int depth, bool live,
                                           float& cr, float& cg, float& cb, int& prim, Sink& sink,
-                                          Cnt&& cnt = Cnt()) {
+                                          Cnt&& cnt = Cnt(), const Shadows& sh = Shadows()) {
   PathState ps;
   ps.r = r;
   ps.T = 1.0f;
   ps.cr = 0.0f; ps.cg = 0.0f; ps.cb = 0.0f;
   ps.from_plane = -1;
   bool alive = live;
-  prim = trace_segment<true, kPrefilter>(s, ps, 0, depth, alive, sink, cnt);
+  prim = trace_segment<true, kPrefilter>(s, ps, 0, depth, alive, sink, cnt, sh);
   int traced = live ? 1 : 0;
   for (int k = 1; k <= depth; ++k) {
     if (!wave_any(alive)) break;
     traced = alive ? k + 1 : traced;
-    trace_segment<false, kPrefilter>(s, ps, k, depth, alive, sink, cnt);
+    trace_segment<false, kPrefilter>(s, ps, k, depth, alive, sink, cnt, sh);
   }
   cr = ps.cr; cg = ps.cg; cb = ps.cb;
   return traced;

@@ -242,6 +242,21 @@ def make_diff_problem(seed: int | None = None, W: int = 1280, H: int = 720, N: i
     return DiffProblem(wl, target)
 
 
+# The paper's benchmark scene has one light, one plane and five spheres whose
+# coordinates it does not print; this seeded stand-in draws five spheres of
+# radius 0.5-1.0 in front of the camera above the ground plane and one light
+# in the usual light box.  PAPER_LIGHT_RADIUS is the radius its soft shadows
+# use (the paper does not give the light's size).
+PAPER_BOX = ((-3.0, -0.5, -10.0), (3.0, 1.5, -4.0))
+PAPER_RADII = (0.5, 1.0)
+PAPER_LIGHT_RADIUS = 0.5
+PAPER_SETTINGS = {"hard_1bounce": (1, 1), "soft200_3bounces": (200, 3)}   # (samples, depth)
+
+
+def paper_scene(seed: int = 2305) -> Scene:
+    return random_scene(np.random.default_rng(seed), 5, 1, box=PAPER_BOX, radii=PAPER_RADII)
+
+
 def tiny_scene(seed: int, n_spheres: int = 3, n_lights: int = 1, with_plane: bool = True,
                spec_model: int = SPEC_BLINN) -> Scene:
     """Small random scene for brute-force and edge-case tests."""

@@ -42,10 +42,13 @@ def gpu_render(rt, scene, cam, W, H, D, records=False):
         h.close()
 
 
-def compare(oracle, scene, cam, W, H, D, gpu, pixels=None, label=""):
-    """Returns a stats dict; raises AssertionError when the parity bar fails."""
-    base = oracle.render(scene, cam, W, H, D, pixels)
-    ok_cond = oracle.condition(scene, cam, W, H, D, pixels, base=base)
+def compare(oracle, scene, cam, W, H, D, gpu, pixels=None, label="", samples=1,
+            light_radius=0.0):
+    """Returns a stats dict; raises AssertionError when the parity bar fails.
+    samples > 1 compares soft shadows of lights of radius light_radius."""
+    base = oracle.render(scene, cam, W, H, D, pixels, samples=samples, light_radius=light_radius)
+    ok_cond = oracle.condition(scene, cam, W, H, D, pixels, base=base, samples=samples,
+                               light_radius=light_radius)
     sel = base.pixels
     g_rgb = gpu["rgb"][sel]
     g_ids = gpu["ids"][sel]
