@@ -242,6 +242,7 @@ rt_status rt_scene_upload(const rt_scene_desc* d, void* stream, rt_scene* out) {
   sc->staging_floats = 9 * N + 9 * P + 4 * L;
   size_t o_stage = take(sc->staging_floats * sizeof(float));
   size_t o_part = take((size_t)blocks * sc->grad_stride * sizeof(float));
+  static_assert(RT_MAX_SAMPLES % 8 == 0, "soft sample table is read in blocks of 8");
   size_t o_soft = take((size_t)RT_MAX_SAMPLES * sizeof(float2));
   sc->bytes = off;
   hipError_t e = hipGetDevice(&sc->device);

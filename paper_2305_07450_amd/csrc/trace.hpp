@@ -914,8 +914,9 @@ struct SoftShadows {
   static constexpr bool kSoft = true;
   int n;                // samples per light
   float radius;         // light radius R
-  const float2* table;  // [n]: sample i in units of R in the disk basis,
-                        // 2 sqrt(i/n) (cos(i phi), sin(i phi)), phi the golden angle
+  const float2* table;  // [n, rounded up to 8]: sample i in units of R in the
+                        // disk basis, 2 sqrt(i/n) (cos(i phi), sin(i phi)), phi the
+                        // golden angle; 64-byte aligned
 };
 
 // Chunks of 64 spheres whose candidate masks a soft-shadow bound keeps; a
@@ -1004,9 +1005,15 @@ __device__ __forceinline__ float soft_visibility(const SceneDev& s, float4 q, co
     }
   }
   int visible = 0;
-  for (int i = 0; i < sh.n; ++i) {
-    const float2 t = ld2(sh.table, i);
-    const float u = sh.radius * t.x, v = sh.radius * t.y;
+  // the table is read 8 samples (64 bytes) per scalar load; it holds a
+  // multiple of 8 entries, so the last block stays inside it
+  for (int i0 = 0; i0 < sh.n; i0 += 8) {
+  const rt_v16 tb = ((const RT_CONSTANT rt_v16*)sh.table)[i0 >> 3];
+#pragma unroll
+  for (int kk = 0; kk < 8; ++kk) {
+    const int i = i0 + kk;
+    if (i >= sh.n) break;
+    const float u = sh.radius * tb[2 * kk], v = sh.radius * tb[2 * kk + 1];
     float dx = fmaf(u, ax, fmaf(v, bx, q.x)) - f.px;
     float dy = fmaf(u, ay, fmaf(v, by, q.y)) - f.py;
     float dz = fmaf(u, az, fmaf(v, bz, q.z)) - f.pz;
@@ -1039,6 +1046,7 @@ __device__ __forceinline__ float soft_visibility(const SceneDev& s, float4 q, co
         blk = blk || (s.n_spheres + j != self && plane_root(ld4(s.pgeom, j), sr, tmin) < di);
     }
     visible += blk ? 0 : 1;
+  }
   }
   return act ? (float)visible / (float)sh.n : 0.0f;
 }
