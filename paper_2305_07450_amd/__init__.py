@@ -31,7 +31,7 @@ RT_MAX_SAMPLES = 4096
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(
-        f"{LIB_PATH} is not built: run `python -m paper_2305_07450_amd.build` "
+        f"{LIB_PATH} is not built: run `python paper_2305_07450_amd/build.py` "
         "(or __graft_entry__.build()); there is no fallback path")
 
 
