@@ -73,7 +73,8 @@ class _Scene(C.Structure):
                 ("plane_mat", C.c_void_p), ("plane_shine", C.c_void_p), ("light", C.c_void_p),
                 ("ambient", C.c_double), ("spec_strength", C.c_double), ("t_min", C.c_double),
                 ("background", C.c_double * 3), ("shadow_samples", C.c_int32),
-                ("light_radius", C.c_double)]
+                ("light_radius", C.c_double), ("sky", C.c_void_p), ("sky_w", C.c_int32),
+                ("sky_h", C.c_int32)]
 
 
 class _Camera(C.Structure):
@@ -144,16 +145,19 @@ class _Pack:
     """Scene promoted exactly from FP32 to FP64, kept alive for the C call;
     `samples` > 1 and `light_radius` select soft shadows."""
 
-    def __init__(self, s: Scene, samples: int = 1, light_radius: float = 0.0):
+    def __init__(self, s: Scene, samples: int = 1, light_radius: float = 0.0, sky=None):
         self.arrays = [np.ascontiguousarray(a, dtype=np.float64) for a in (
             s.sphere_geom, s.sphere_mat, s.sphere_shine, s.plane_geom, s.plane_mat,
             s.plane_shine, s.light)]
         a = self.arrays
+        self.sky = (np.ascontiguousarray(sky, dtype=np.float64) if sky is not None
+                    else np.zeros((0, 0, 3)))
         self.c = _Scene(s.n_spheres, s.n_planes, s.n_lights, int(s.spec_model),
                         _ptr(a[0]), _ptr(a[1]), _ptr(a[2]), _ptr(a[3]), _ptr(a[4]), _ptr(a[5]),
                         _ptr(a[6]), float(s.ambient), float(s.spec_strength), float(s.t_min),
                         (C.c_double * 3)(*[float(v) for v in s.background]), int(samples),
-                        float(light_radius))
+                        float(light_radius), _ptr(self.sky), int(self.sky.shape[1]),
+                        int(self.sky.shape[0]))
 
 
 def _cam(cam: Camera) -> _Camera:
@@ -177,9 +181,10 @@ class Result(dict):
 def render(scene: Scene, cam: Camera, W: int, H: int, depth: int,
            pixels: Optional[np.ndarray] = None, records: bool = True, margins: bool = True,
            jitter: float = 0.0, seed: int = 0, threads: Optional[int] = None,
-           samples: int = 1, light_radius: float = 0.0) -> Result:
+           samples: int = 1, light_radius: float = 0.0, sky=None) -> Result:
     """Render the listed pixels (flat indices y*W+x; default all) in FP64;
-    samples > 1 renders soft shadows of lights of radius light_radius.
+    samples > 1 renders soft shadows of lights of radius light_radius; `sky`
+    (an [h, w, 3] map) replaces the background colour of misses.
 
     Returns rgb [n,3] float64, prim_id [n], seg_id [n,depth+1], lit [n,depth+1],
     margin [n] and the algorithmic counters (dict)."""
@@ -192,7 +197,7 @@ def render(scene: Scene, cam: Camera, W: int, H: int, depth: int,
     lit = np.zeros((n, depth + 1), np.uint32) if records else np.zeros(0, np.uint32)
     mar = np.zeros(n, np.float64) if margins else np.zeros(0, np.float64)
     cnt = np.zeros(len(CNT_NAMES), np.int64)
-    sp = _Pack(scene, samples, light_radius)
+    sp = _Pack(scene, samples, light_radius, sky)
     out = _Outputs(_ptr(rgb), _ptr(prim), _ptr(seg) if records else 0,
                    _ptr(lit) if records else 0, _ptr(mar) if margins else 0, _ptr(cnt))
     rc = lib().or_render_pixels(C.byref(sp.c), C.byref(_cam(cam)), W, H, depth, n, _ptr(pix),
@@ -212,20 +217,20 @@ def condition(scene: Scene, cam: Camera, W: int, H: int, depth: int,
               pixels: Optional[np.ndarray] = None, base: Optional[Result] = None,
               runs: int = COND_RUNS, jitter: float = JITTER, spread: float = COND_SPREAD,
               threads: Optional[int] = None, samples: int = 1,
-              light_radius: float = 0.0) -> np.ndarray:
+              light_radius: float = 0.0, sky=None) -> np.ndarray:
     """Boolean mask of well-conditioned pixels: every jittered re-trace keeps
     the same decision record and the colour spread stays within `spread`.
     With soft shadows every sample ray moves with its segment, so a pixel
     whose visible sample count changes shows a colour spread."""
     if base is None:
         base = render(scene, cam, W, H, depth, pixels, threads=threads, samples=samples,
-                      light_radius=light_radius)
+                      light_radius=light_radius, sky=sky)
     ok = np.ones(base.rgb.shape[0], bool)
     lo, hi = base.rgb.copy(), base.rgb.copy()
     for k in range(runs):
         r = render(scene, cam, W, H, depth, base.pixels, margins=False, jitter=jitter,
                    seed=0x5EED0000 + k, threads=threads, samples=samples,
-                   light_radius=light_radius)
+                   light_radius=light_radius, sky=sky)
         ok &= (r.seg_id == base.seg_id).all(1) & (r.lit == base.lit).all(1)
         lo = np.minimum(lo, r.rgb)
         hi = np.maximum(hi, r.rgb)

@@ -33,7 +33,11 @@
  *     and specular are scaled by the unblocked share; a sample behind the
  *     tangent plane at p is blocked; the shading direction is the centre's;
  *   - the view vector on every bounce is minus the incoming ray direction;
- *   - a miss returns the background colour (black by default).
+ *   - a miss returns the background colour (black by default), or with a
+ *     skybox (Section 3.8) the map's colour in the ray's direction by the
+ *     textbook spherical UV mapping (longitude from atan2, latitude from
+ *     asin, straight ahead at the map's centre), filtered bilinearly: the
+ *     paper names UV mapping but gives neither the axes nor the filter.
  */
 #include "rt_oracle.h"
 
@@ -277,6 +281,38 @@ static uint32_t light_terms(const or_scene* s, const double p[3], const double n
   return lit;
 }
 
+/* ---- Section 3.8: skybox --------------------------------------------------- */
+
+/* Colour of the map in direction d (unit), by spherical UV mapping: the
+ * longitude u = 1/2 + atan2(d_x, -d_z) / (2 pi) (u = 1/2 straight ahead, down
+ * -z) and the latitude v = 1/2 - asin(d_y) / pi (v = 0 straight up) index an
+ * equirectangular image, whose texel (i, j) covers u in [i/w, (i+1)/w) and v
+ * in [j/h, (j+1)/h); bilinear between texel centres, wrapping around in u and
+ * clamped to the first and last row in v. */
+static void sky_colour(const or_scene* s, const double d[3], double out[3]) {
+  double u = 0.5 + atan2(d[0], -d[2]) / (2.0 * OR_PI);
+  double dy = d[1] < -1.0 ? -1.0 : (d[1] > 1.0 ? 1.0 : d[1]);
+  double v = 0.5 - asin(dy) / OR_PI;
+  double x = u * s->sky_w - 0.5, y = v * s->sky_h - 0.5;
+  double fx = floor(x), fy = floor(y);
+  double ax = x - fx, ay = y - fy;
+  int64_t x0 = (int64_t)fx, y0 = (int64_t)fy;
+  int64_t xs[2], ys[2];
+  for (int k = 0; k < 2; ++k) {
+    int64_t xi = (x0 + k) % s->sky_w;
+    xs[k] = xi < 0 ? xi + s->sky_w : xi;
+    int64_t yi = y0 + k;
+    ys[k] = yi < 0 ? 0 : (yi >= s->sky_h ? s->sky_h - 1 : yi);
+  }
+  for (int c = 0; c < 3; ++c) {
+    double t00 = s->sky[3 * (ys[0] * s->sky_w + xs[0]) + c];
+    double t10 = s->sky[3 * (ys[0] * s->sky_w + xs[1]) + c];
+    double t01 = s->sky[3 * (ys[1] * s->sky_w + xs[0]) + c];
+    double t11 = s->sky[3 * (ys[1] * s->sky_w + xs[1]) + c];
+    out[c] = (1.0 - ay) * ((1.0 - ax) * t00 + ax * t10) + ay * ((1.0 - ax) * t01 + ax * t11);
+  }
+}
+
 /* ---- Section 3.7: recursive reflections --------------------------------- */
 
 typedef struct {
@@ -325,9 +361,13 @@ static void ray_trace(const or_scene* s, const double o_in[3], const double d_in
   int32_t id = or_closest_hit(s, o, d, &t, c->counts);
   if (c->seg_id) c->seg_id[level] = id;
   if (id == OR_MISS) {
-    color[0] = s->background[0];
-    color[1] = s->background[1];
-    color[2] = s->background[2];
+    if (s->sky && s->sky_w > 0 && s->sky_h > 0) {
+      sky_colour(s, d, color);
+    } else {
+      color[0] = s->background[0];
+      color[1] = s->background[1];
+      color[2] = s->background[2];
+    }
     return;
   }
   double p[3] = {o[0] + t * d[0], o[1] + t * d[1], o[2] + t * d[2]};

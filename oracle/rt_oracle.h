@@ -52,6 +52,10 @@ typedef struct {
    * great circle facing the hit point; 0 or 1 sample: hard shadows. */
   int32_t shadow_samples;
   double light_radius;
+  /* Skybox (Section 3.8): an equirectangular map sky[h][w][3] that replaces
+   * the background colour of a miss; NULL (or w = 0): the background. */
+  const double* sky;
+  int32_t sky_w, sky_h;
 } or_scene;
 
 typedef struct {

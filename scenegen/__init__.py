@@ -253,6 +253,31 @@ PAPER_LIGHT_RADIUS = 0.5
 PAPER_SETTINGS = {"hard_1bounce": (1, 1), "soft200_3bounces": (200, 3)}   # (samples, depth)
 
 
+def sky_map(seed: int = 38, w: int = 512, h: int = 256) -> np.ndarray:
+    """Procedural equirectangular sky, float32 [h, w, 3], standing in for the
+    paper's HDR skybox image: a vertical gradient (light at the horizon,
+    deeper blue overhead, dark ground below), a bright sun about 5 degrees
+    across and seeded low-frequency variation, all smooth over several texels."""
+    rng = np.random.default_rng(seed)
+    v = (np.arange(h) + 0.5) / h                 # 0 at the top
+    u = (np.arange(w) + 0.5) / w
+    lat = (0.5 - v)[:, None] * np.pi             # +pi/2 overhead
+    lon = (u - 0.5)[None, :] * 2 * np.pi
+    up = np.clip(np.sin(lat), -1, 1)
+    sky = np.where(up[..., None] >= 0,
+                   np.array([0.55, 0.70, 0.95]) * (1 - up[..., None]) ** 2
+                   + np.array([0.10, 0.25, 0.70]) * (1 - (1 - up[..., None]) ** 2),
+                   np.array([0.25, 0.22, 0.20]) * (1 + up[..., None]))
+    sky = np.broadcast_to(sky, (h, w, 3)).copy()
+    ph = rng.uniform(0, 2 * np.pi, size=(3, 2))
+    for k, (a, b) in enumerate(ph):
+        sky += 0.04 * (np.sin((k + 1) * lon + a) * np.cos((k + 2) * lat + b))[..., None]
+    s_lon, s_lat = rng.uniform(-0.6, 0.6), rng.uniform(0.35, 0.7)
+    cosang = (np.cos(lat) * np.cos(s_lat) * np.cos(lon - s_lon) + np.sin(lat) * np.sin(s_lat))
+    sky += 2.0 * np.exp((cosang - 1.0) / 0.004)[..., None] * np.array([1.0, 0.95, 0.85])
+    return np.clip(sky, 0.0, None).astype(F32)
+
+
 def paper_scene(seed: int = 2305) -> Scene:
     return random_scene(np.random.default_rng(seed), 5, 1, box=PAPER_BOX, radii=PAPER_RADII)
 
