@@ -194,21 +194,26 @@ def bench_paper_scene(rt, scenegen, stream, reps=10):
     """The paper's benchmark scene (a seeded stand-in with its shape: one light,
     one plane, five spheres) at 720p, 1080p and 4K in its two settings: one
     shadow sample with one bounce (its GUI runs), and 200 samples of a
-    spherical light with three bounces (its non-GUI runs)."""
+    spherical light with three bounces (its non-GUI runs); each with the plain
+    background and with a skybox (a procedural 512x256 equirectangular map
+    standing in for the paper's HDR image)."""
     s = scenegen.paper_scene()
     h = rt.SceneHandle(s)
     cam = scenegen.Camera()
-    out = {"light_radius": scenegen.PAPER_LIGHT_RADIUS}
-    for name, (n, D) in scenegen.PAPER_SETTINGS.items():
-        res = {}
-        for W, H in PAPER_SIZES:
-            rgb = torch_empty_image(H, W)
-            ms = time_gpu(lambda: rt.rt_render_soft(h.handle, cam, W, H, D, n,
-                                                    scenegen.PAPER_LIGHT_RADIUS, rgb, None, 0,
-                                                    stream), reps, 2, stream)
-            res[f"{W}x{H}"] = {"ms": round(ms, 4), "fps": round(1e3 / ms, 1),
-                               "primary_mrays_per_s": round(W * H / (ms * 1e-3) / 1e6, 1)}
-        out[name] = {"samples": n, "depth": D, **res}
+    out = {"light_radius": scenegen.PAPER_LIGHT_RADIUS, "skybox": "procedural 512x256"}
+    for sky in (False, True):
+        if sky:
+            rt.rt_scene_set_sky(h.handle, scenegen.sky_map())
+        for name, (n, D) in scenegen.PAPER_SETTINGS.items():
+            res = {}
+            for W, H in PAPER_SIZES:
+                rgb = torch_empty_image(H, W)
+                ms = time_gpu(lambda: rt.rt_render_soft(h.handle, cam, W, H, D, n,
+                                                        scenegen.PAPER_LIGHT_RADIUS, rgb, None,
+                                                        0, stream), reps, 2, stream)
+                res[f"{W}x{H}"] = {"ms": round(ms, 4), "fps": round(1e3 / ms, 1),
+                                   "primary_mrays_per_s": round(W * H / (ms * 1e-3) / 1e6, 1)}
+            out[name + ("_skybox" if sky else "")] = {"samples": n, "depth": D, **res}
     h.close()
     return out
 

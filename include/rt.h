@@ -45,6 +45,7 @@ extern "C" {
 #define RT_MAX_DIM 16384      /* largest W or H                                 */
 #define RT_MAX_BATCH 4096     /* largest number of scenes in one batch          */
 #define RT_MAX_SAMPLES 4096   /* most shadow samples per light (rt_render_soft)  */
+#define RT_MAX_SKY_DIM 16384  /* largest skybox width or height                 */
 
 typedef enum {
   RT_OK = 0,
@@ -134,6 +135,27 @@ rt_status rt_scene_upload(const rt_scene_desc* desc, void* stream, rt_scene* out
  * mem == RT_DEVICE. */
 rt_status rt_scene_update(rt_scene scene, const rt_scene_desc* desc, void* stream);
 
+/* Give a scene a skybox (Section 3.8): a distant panoramic HDR image that a
+ * ray leaving the scene shows in place of the plain background.  `rgb` is
+ * float32 [h][w][3], linear colour, finite (checked when mem == RT_HOST),
+ * equirectangular: for a unit
+ * direction d, column coordinate u = 1/2 + atan2(d_x, -d_z) / (2 pi) and row
+ * coordinate v = 1/2 - asin(d_y) / pi, both in [0, 1] across the whole image
+ * (row 0 straight up, u = 1/2 along -z); the colour is bilinear between
+ * texel centres (x = u w - 1/2, y = v h - 1/2), wrapping around in x and
+ * clamped to the edge rows in y.  Every render entry point then uses it on
+ * a miss; rt_render_backward refuses scenes with a skybox
+ * (RT_ERR_UNSUPPORTED).
+ *   rgb   host or device pointer per `mem`; copied, the caller keeps it;
+ *   w, h  1 .. RT_MAX_SKY_DIM; rgb == NULL with w == h == 0 removes the
+ *         skybox.
+ * Allocates the skybox's own device buffer when the scene has none of this
+ * size (frees it on removal); not capture-safe.  With mem == RT_HOST the copy
+ * is synchronous; with RT_DEVICE it is ordered on `stream`.  Renders already
+ * queued on other streams must be finished first. */
+rt_status rt_scene_set_sky(rt_scene scene, const float* rgb, int32_t w, int32_t h, rt_mem mem,
+                           void* stream);
+
 rt_status rt_scene_destroy(rt_scene scene);
 
 /* Bytes of records for a W x H image at the given depth. */
@@ -202,8 +224,8 @@ rt_status rt_render_counts(rt_scene scene, const rt_camera* cam, int32_t W, int3
  * shadow occluders carry no gradient.  With rec == NULL the decisions are
  * recomputed by re-tracing; otherwise they are read from records written by
  * rt_render for the same scene, camera, size and depth.  The sum over pixels
- * is deterministic (fixed order, no floating-point atomics).  No
- * allocation; capture-safe. */
+ * is deterministic (fixed order, no floating-point atomics).  A scene with
+ * a skybox is refused (RT_ERR_UNSUPPORTED).  No allocation; capture-safe. */
 rt_status rt_render_backward(rt_scene scene, const rt_camera* cam, int32_t W, int32_t H,
                              int32_t depth, const float* grad_rgb, const rt_records* rec,
                              const rt_grads* grads, void* stream);
@@ -222,10 +244,14 @@ rt_status rt_batch_create(int32_t n, const rt_scene* scenes, const rt_camera* ca
                           float* const* rgb_out, int32_t autotune, void* stream, rt_batch* out);
 
 /* Replay the batch's graph on `stream`.  Scenes may be updated in place
- * between launches. */
+ * between launches (rt_scene_update, and rt_scene_set_sky with the size the
+ * skybox had at creation); a skybox added, removed or resized since
+ * rt_batch_create makes the launch return RT_ERR_INVALID_ARG.  The scenes
+ * must outlive the batch. */
 rt_status rt_batch_launch(rt_batch batch, void* stream);
 
-/* The same launch without the graph (a plain kernel launch). */
+/* The same launch without the graph (a plain kernel launch), with the same
+ * skybox check. */
 rt_status rt_batch_launch_direct(rt_batch batch, void* stream);
 
 /* Launch shape chosen for the batch: workgroups and pixel-tile width and

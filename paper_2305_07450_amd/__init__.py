@@ -28,6 +28,7 @@ RT_MAX_SPHERES = 4096
 RT_MAX_PLANES = 16
 RT_RENDER_NO_PREFILTER = 1
 RT_MAX_SAMPLES = 4096
+RT_MAX_SKY_DIM = 16384
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(
@@ -71,6 +72,7 @@ _i32 = C.c_int32
 _sig = {
     "rt_scene_upload": (C.c_int, [C.POINTER(rt_scene_desc), _vp, C.POINTER(_vp)]),
     "rt_scene_update": (C.c_int, [_vp, C.POINTER(rt_scene_desc), _vp]),
+    "rt_scene_set_sky": (C.c_int, [_vp, _vp, _i32, _i32, C.c_int, _vp]),
     "rt_scene_destroy": (C.c_int, [_vp]),
     "rt_records_bytes": (C.c_int64, [_i32, _i32, _i32]),
     "rt_render": (C.c_int, [_vp, C.POINTER(rt_camera), _i32, _i32, _i32, _vp, _vp,
@@ -179,6 +181,27 @@ def rt_scene_update(handle: int, scene, stream=None, arrays: Optional[Dict[str, 
     d = _Desc(scene, arrays)
     _check(_lib.rt_scene_update(handle, C.byref(d.c), _stream(stream)))
     return d   # caller keeps device arrays alive until the stream has consumed them
+
+
+def rt_scene_set_sky(handle: int, rgb=None, stream=None):
+    """Give the scene a skybox, float32 [h, w, 3] (numpy -> RT_HOST, CUDA
+    tensor -> RT_DEVICE), or remove it (rgb None)."""
+    if rgb is None:
+        _check(_lib.rt_scene_set_sky(handle, None, 0, 0, 0, _stream(stream)))
+        return None
+    if isinstance(rgb, torch.Tensor):
+        if rgb.dtype != torch.float32 or not rgb.is_contiguous() or rgb.dim() != 3 \
+                or rgb.shape[2] != 3:
+            raise ValueError("skybox tensor must be contiguous float32 [h, w, 3]")
+        arr, mem = rgb, 1 if rgb.is_cuda else 0
+    else:
+        arr = np.ascontiguousarray(rgb, dtype=np.float32)
+        if arr.ndim != 3 or arr.shape[2] != 3:
+            raise ValueError("skybox must be [h, w, 3]")
+        mem = 0
+    _check(_lib.rt_scene_set_sky(handle, _ptr(arr), int(arr.shape[1]), int(arr.shape[0]), mem,
+                                 _stream(stream)))
+    return arr   # with RT_DEVICE the caller keeps it alive until the stream has consumed it
 
 
 def rt_scene_destroy(handle: int):

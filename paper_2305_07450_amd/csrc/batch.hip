@@ -59,6 +59,7 @@ __global__ void batch_cone_kernel(const BatchJob* __restrict__ jobs, float4* con
   }
 }
 
+template <class Bg>
 __global__ __launch_bounds__(256) void batch_kernel(const BatchJob* __restrict__ jobs,
                                                      const TileRef* __restrict__ queue,
                                                      int n_tiles, unsigned int* counter,
@@ -96,8 +97,9 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchJob* __restrict__
       float cr, cg, cb;
       int prim;
       NoRecords sink;
-      trace_path(job.s, primary_ray(job.c, live ? x : job.c.W - 1, live ? y : job.c.H - 1),
-                 job.depth, live, cr, cg, cb, prim, sink);
+      trace_path<NoRecords, NoCount, true, HardShadows, Bg>(
+          job.s, primary_ray(job.c, live ? x : job.c.W - 1, live ? y : job.c.H - 1), job.depth,
+          live, cr, cg, cb, prim, sink);
       if (live) {
         const int64_t pix = (int64_t)y * job.c.W + x;
         job.rgb[3 * pix + 0] = cr;
@@ -124,7 +126,9 @@ struct rt_batch_s {
   int max_spheres = 0;
   unsigned int* counter = nullptr;
   std::vector<BatchJob> host_jobs;
+  std::vector<const rt_scene_s*> scenes;  // the skybox each job was built with is in host_jobs
   std::vector<double> job_cost;  // per tile
+  bool any_sky = false;          // some job's scene has a skybox
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -179,8 +183,9 @@ hipError_t launch_batch(rt_batch_s* b, hipStream_t stream) {
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(batch_kernel, dim3(b->shape.grid), dim3(64 * b->shape.waves), 0, stream,
-                     b->jobs, b->queue, b->n_tiles, b->counter, b->shape.wave_w);
+  auto kern = b->any_sky ? batch_kernel<SkyBackground> : batch_kernel<PlainBackground>;
+  hipLaunchKernelGGL(kern, dim3(b->shape.grid), dim3(64 * b->shape.waves), 0, stream, b->jobs,
+                     b->queue, b->n_tiles, b->counter, b->shape.wave_w);
   return hipGetLastError();
 }
 
@@ -189,7 +194,7 @@ std::string signature(const rt_batch_s* b) {
   for (const BatchJob& j : b->host_jobs)
     s += ":" + std::to_string(j.c.W) + "x" + std::to_string(j.c.H) + "d" +
          std::to_string(j.depth) + "n" + std::to_string(j.s.n_spheres) + "l" +
-         std::to_string(j.s.n_lights);
+         std::to_string(j.s.n_lights) + (j.s.sky ? "s" : "");
   return s;
 }
 
@@ -289,6 +294,8 @@ rt_status rt_batch_create(int32_t n, const rt_scene* scenes, const rt_camera* ca
     j.tiles_x = 0;
     j.rgb = rgb_out[i];
     b->host_jobs.push_back(j);
+    b->scenes.push_back(scenes[i]);
+    b->any_sky = b->any_sky || scenes[i]->sky != nullptr;
     const rt_scene_s* sc = scenes[i];
     b->job_cost.push_back(64.0 * (depth[i] + 1) * (sc->n_spheres + sc->n_planes + 1) *
                           (1 + sc->n_lights));
@@ -372,13 +379,31 @@ rt_status rt_batch_create(int32_t n, const rt_scene* scenes, const rt_camera* ca
   return RT_OK;
 }
 
+// The job descriptors hold each scene's skybox pointer and size as they were
+// at creation; a skybox set, removed or resized since then would be read
+// through a stale pointer, so the launch refuses it.
+static rt_status check_skies(const rt_batch_s* b) {
+  for (int i = 0; i < b->n; ++i) {
+    const rt_scene_s* sc = b->scenes[i];
+    const SceneDev& s = b->host_jobs[i].s;
+    if (sc->sky != s.sky || sc->sky_w != s.sky_w || sc->sky_h != s.sky_h)
+      return err(RT_ERR_INVALID_ARG, "the skybox of scene " + std::to_string(i) +
+                                         " changed since the batch was created");
+  }
+  return RT_OK;
+}
+
 rt_status rt_batch_launch(rt_batch b, void* stream) {
   if (!b) return err(RT_ERR_INVALID_ARG, "batch is NULL");
+  rt_status st = check_skies(b);
+  if (st != RT_OK) return st;
   return hip_fail(hipGraphLaunch(b->exec, (hipStream_t)stream), "batch graph launch");
 }
 
 rt_status rt_batch_launch_direct(rt_batch b, void* stream) {
   if (!b) return err(RT_ERR_INVALID_ARG, "batch is NULL");
+  rt_status st = check_skies(b);
+  if (st != RT_OK) return st;
   return hip_fail(launch_batch(b, (hipStream_t)stream), "batch launch");
 }
 

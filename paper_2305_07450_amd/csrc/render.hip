@@ -27,7 +27,7 @@ struct RecordSink {
   __device__ __forceinline__ void lit(int k, uint32_t m) { lit_plane[k * plane + pix] = (uint8_t)m; }
 };
 
-template <bool kRecords, bool kPrefilter>
+template <bool kRecords, bool kPrefilter, class Bg>
 __global__ __launch_bounds__(256) void render_kernel(SceneDev s, CameraDev c, int depth,
                                                       float* __restrict__ rgb,
                                                       int32_t* __restrict__ id_out,
@@ -47,7 +47,8 @@ __global__ __launch_bounds__(256) void render_kernel(SceneDev s, CameraDev c, in
   int prim;
   if (kRecords) {
     RecordSink sink{rec_ids, rec_lit, (int64_t)c.W * c.H, pix};
-    int traced = trace_path<RecordSink, NoCount, kPrefilter>(s, r, depth, live, cr, cg, cb, prim, sink);
+    int traced = trace_path<RecordSink, NoCount, kPrefilter, HardShadows, Bg>(s, r, depth, live, cr,
+                                                                              cg, cb, prim, sink);
     if (live) {
       for (int k = traced; k <= depth; ++k) {
         rec_ids[k * sink.plane + pix] = kNotTraced;
@@ -56,7 +57,8 @@ __global__ __launch_bounds__(256) void render_kernel(SceneDev s, CameraDev c, in
     }
   } else {
     NoRecords sink;
-    trace_path<NoRecords, NoCount, kPrefilter>(s, r, depth, live, cr, cg, cb, prim, sink);
+    trace_path<NoRecords, NoCount, kPrefilter, HardShadows, Bg>(s, r, depth, live, cr, cg, cb, prim,
+                                                                sink);
   }
   if (live) {
     rgb[3 * pix + 0] = cr;
@@ -67,7 +69,7 @@ __global__ __launch_bounds__(256) void render_kernel(SceneDev s, CameraDev c, in
 }
 
 // Soft-shadow render: the same paths with every light sampled (SoftShadows).
-template <bool kPrefilter>
+template <bool kPrefilter, class Bg>
 __global__ __launch_bounds__(256) void render_soft_kernel(SceneDev s, CameraDev c, int depth,
                                                            SoftShadows sh,
                                                            float* __restrict__ rgb,
@@ -83,8 +85,8 @@ __global__ __launch_bounds__(256) void render_soft_kernel(SceneDev s, CameraDev 
   float cr, cg, cb;
   int prim;
   NoRecords sink;
-  trace_path<NoRecords, NoCount, kPrefilter, SoftShadows>(s, r, depth, live, cr, cg, cb, prim,
-                                                          sink, NoCount(), sh);
+  trace_path<NoRecords, NoCount, kPrefilter, SoftShadows, Bg>(s, r, depth, live, cr, cg, cb, prim,
+                                                              sink, NoCount(), sh);
   if (live) {
     rgb[3 * pix + 0] = cr;
     rgb[3 * pix + 1] = cg;
@@ -119,7 +121,11 @@ hipError_t launch_render_soft(const rt_scene_s& sc, const CameraDev& c, int dept
   sh.radius = radius;
   sh.table = sc.soft_table;
   dim3 grid((c.W + kBlock - 1) / kBlock, (c.H + kBlock - 1) / kBlock);
-  auto kern = prefilter ? render_soft_kernel<true> : render_soft_kernel<false>;
+  const bool sky = sc.sky != nullptr;
+  auto kern = sky ? (prefilter ? render_soft_kernel<true, SkyBackground>
+                               : render_soft_kernel<false, SkyBackground>)
+                  : (prefilter ? render_soft_kernel<true, PlainBackground>
+                               : render_soft_kernel<false, PlainBackground>);
   hipLaunchKernelGGL(kern, grid, dim3(256), 0, stream, sc.view(), c, depth, sh, rgb, ids);
   return hipGetLastError();
 }
@@ -160,8 +166,15 @@ hipError_t launch_render(const SceneDev& s, const CameraDev& c, int depth, float
                          int32_t* ids, int32_t* rec_ids, uint8_t* rec_lit, bool prefilter,
                          hipStream_t stream) {
   dim3 grid((c.W + kBlock - 1) / kBlock, (c.H + kBlock - 1) / kBlock);
-  auto kern = rec_ids ? (prefilter ? render_kernel<true, true> : render_kernel<true, false>)
-                      : (prefilter ? render_kernel<false, true> : render_kernel<false, false>);
+  using P = PlainBackground;
+  using K = SkyBackground;
+  decltype(&render_kernel<false, true, P>) kern;
+  if (s.sky)
+    kern = rec_ids ? (prefilter ? render_kernel<true, true, K> : render_kernel<true, false, K>)
+                   : (prefilter ? render_kernel<false, true, K> : render_kernel<false, false, K>);
+  else
+    kern = rec_ids ? (prefilter ? render_kernel<true, true, P> : render_kernel<true, false, P>)
+                   : (prefilter ? render_kernel<false, true, P> : render_kernel<false, false, P>);
   hipLaunchKernelGGL(kern, grid, dim3(256), 0, stream, s, c, depth, rgb, ids, rec_ids, rec_lit);
   return hipGetLastError();
 }
@@ -212,6 +225,18 @@ hipError_t launch_pack(const rt_scene_s& sc, const RawScene& raw, hipStream_t st
   hipLaunchKernelGGL(pack_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, raw,
                      sc.n_spheres, sc.n_planes, sc.n_lights, sc.geom, sc.rad, sc.mat, sc.shine,
                      sc.pgeom, sc.light, sc.light_cone);
+  return hipGetLastError();
+}
+
+__global__ void sky_pack_kernel(const float* __restrict__ rgb, float4* __restrict__ sky,
+                                int texels) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < texels) sky[i] = make_float4(rgb[3 * i], rgb[3 * i + 1], rgb[3 * i + 2], 0.0f);
+}
+
+hipError_t launch_sky_pack(const float* rgb, float4* sky, int texels, hipStream_t stream) {
+  hipLaunchKernelGGL(sky_pack_kernel, dim3((texels + 255) / 256), dim3(256), 0, stream, rgb, sky,
+                     texels);
   return hipGetLastError();
 }
 

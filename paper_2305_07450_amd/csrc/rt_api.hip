@@ -8,6 +8,7 @@
 
 #include <mutex>
 #include <new>
+#include <vector>
 
 #include <cmath>
 
@@ -283,10 +284,58 @@ rt_status rt_scene_update(rt_scene sc, const rt_scene_desc* d, void* stream) {
   return upload_values(sc, d, (hipStream_t)stream);
 }
 
+rt_status rt_scene_set_sky(rt_scene sc, const float* rgb, int32_t w, int32_t h, rt_mem mem,
+                           void* stream) {
+  if (!sc) return fail(RT_ERR_INVALID_ARG, "scene is NULL");
+  if (!rgb && w == 0 && h == 0) {
+    hipError_t e = sc->sky ? hipFree(sc->sky) : hipSuccess;
+    sc->sky = nullptr;
+    sc->sky_w = sc->sky_h = 0;
+    return hip_fail(e, "skybox free");
+  }
+  if (!rgb) return fail(RT_ERR_INVALID_ARG, "skybox is NULL");
+  if (w < 1 || h < 1 || w > RT_MAX_SKY_DIM || h > RT_MAX_SKY_DIM)
+    return fail(RT_ERR_INVALID_ARG, "skybox %dx%d outside [1, %d]", w, h, RT_MAX_SKY_DIM);
+  if (mem != RT_HOST && mem != RT_DEVICE) return fail(RT_ERR_INVALID_ARG, "mem=%d", (int)mem);
+  const size_t texels = (size_t)w * h;
+  if (mem == RT_HOST && !finite_all(rgb, 3 * (int64_t)texels))
+    return fail(RT_ERR_INVALID_ARG, "non-finite value in the skybox");
+  hipStream_t st = (hipStream_t)stream;
+  if (sc->sky && (sc->sky_w != w || sc->sky_h != h)) {
+    hipError_t e = hipFree(sc->sky);
+    sc->sky = nullptr;
+    sc->sky_w = sc->sky_h = 0;
+    if (e != hipSuccess) return hip_fail(e, "skybox free");
+  }
+  if (!sc->sky) {
+    hipError_t e = hipMalloc(&sc->sky, texels * sizeof(float4));
+    if (e != hipSuccess) {
+      sc->sky = nullptr;
+      return hip_fail(e, "skybox allocation");
+    }
+  }
+  sc->sky_w = w;
+  sc->sky_h = h;
+  if (mem == RT_HOST) {
+    std::vector<float4> tex(texels);
+    for (size_t i = 0; i < texels; ++i)
+      tex[i] = make_float4(rgb[3 * i], rgb[3 * i + 1], rgb[3 * i + 2], 0.0f);
+    HIP_TRY(hipMemcpyAsync(sc->sky, tex.data(), texels * sizeof(float4), hipMemcpyHostToDevice,
+                           st),
+            "skybox upload");
+    HIP_TRY(hipStreamSynchronize(st), "skybox upload sync");
+  } else {
+    HIP_TRY(launch_sky_pack(rgb, sc->sky, (int)texels, st), "skybox pack kernel");
+  }
+  return RT_OK;
+}
+
 rt_status rt_scene_destroy(rt_scene sc) {
   if (!sc) return RT_OK;
   hipError_t e = hipFree(sc->buffer);
+  hipError_t e2 = sc->sky ? hipFree(sc->sky) : hipSuccess;
   delete sc;
+  if (e == hipSuccess) e = e2;
   return hip_fail(e, "scene free");
 }
 
@@ -373,6 +422,9 @@ rt_status rt_render_backward(rt_scene sc, const rt_camera* cam, int32_t W, int32
   if (!grad_rgb) return fail(RT_ERR_INVALID_ARG, "grad_rgb is NULL");
   if (!grads) return fail(RT_ERR_INVALID_ARG, "grads is NULL");
   if ((st = check_records(rec, W, H, depth)) != RT_OK) return st;
+  if (sc->sky)
+    return fail(RT_ERR_UNSUPPORTED, "rt_render_backward does not differentiate a skybox; remove it "
+                "with rt_scene_set_sky(scene, NULL, 0, 0, ...)");
   if (!adjoint_supported(sc->n_spheres))
     return fail(RT_ERR_UNSUPPORTED, "rt_render_backward supports at most 2335 spheres, scene has %d",
                 sc->n_spheres);

@@ -32,6 +32,8 @@ struct rt_scene_s {
   float2* soft_table = nullptr; // [RT_MAX_SAMPLES] shadow sample points of the last soft render
   float* partials = nullptr;    // adjoint partials [kAdjointBlocks][grad_stride]
   int grad_stride = 0;          // 7N + 4L (padded)
+  float4* sky = nullptr;        // own hipMalloc: [sky_h][sky_w] rgb + unused, or none
+  int sky_w = 0, sky_h = 0;
 
   rtk::SceneDev view() const {
     rtk::SceneDev s;
@@ -42,6 +44,7 @@ struct rt_scene_s {
     s.spec_model = spec_model;
     s.ambient = ambient; s.spec_strength = spec_strength; s.t_min = t_min;
     s.bg_r = bg[0]; s.bg_g = bg[1]; s.bg_b = bg[2];
+    s.sky = sky; s.sky_w = sky_w; s.sky_h = sky_h;
     return s;
   }
 };
@@ -67,6 +70,9 @@ struct RawScene {
 };
 
 hipError_t launch_pack(const rt_scene_s& sc, const RawScene& raw, hipStream_t stream);
+
+// Repack a device skybox [h][w][3] into the scene's float4 texels.
+hipError_t launch_sky_pack(const float* rgb, float4* sky, int texels, hipStream_t stream);
 
 // Cones of every sphere seen from the camera's eye, into sc.eye_cone.
 hipError_t launch_eye_cones(const rt_scene_s& sc, const CameraDev& c, hipStream_t stream);

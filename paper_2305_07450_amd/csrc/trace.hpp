@@ -41,6 +41,8 @@ struct SceneDev {
   int n4;   // sphere tables padded to a multiple of kGroup (+kGroup for prefetch)
   float ambient, spec_strength, t_min;
   float bg_r, bg_g, bg_b;
+  const float4* sky;     // [sky_h][sky_w] rgb, unused; NULL: plain background
+  int sky_w, sky_h;
 };
 
 // Sphere tables (geom, eye_cone, light_cone) hold n4 = round_up(N, kGroup)
@@ -1115,6 +1117,61 @@ __device__ __forceinline__ void reflect_ray(Ray& r, const Surface& f) {
   r.ox = f.px; r.oy = f.py; r.oz = f.pz;
 }
 
+// Colour of the skybox (Section 3.8) in unit direction d: an equirectangular
+// map, longitude u = 1/2 + atan2(d_x, -d_z) / (2 pi) across its width (the
+// seam behind the default camera, which looks along -z), latitude
+// v = 1/2 - asin(d_y) / pi down its height (row 0 is straight up), read with
+// bilinear weights between texel centres, wrapping in u and clamping in v.
+// Only lanes whose ray left the scene call it; the four taps are vector loads
+// of one float4 texel each.  Every index is clamped into the map, so even a
+// non-finite direction reads inside it.
+__device__ __forceinline__ void sky_colour(const SceneDev& s, float dx, float dy, float dz,
+                                           float& r, float& g, float& b) {
+  constexpr float kInvTwoPi = 0.15915494309189535f;
+  constexpr float kInvPi = 0.3183098861837907f;
+  const int w = s.sky_w, h = s.sky_h;
+  const float u = fmaf(atan2f(dx, -dz), kInvTwoPi, 0.5f);
+  const float v = fmaf(-asinf(fminf(fmaxf(dy, -1.0f), 1.0f)), kInvPi, 0.5f);
+  const float x = fmaf(u, (float)w, -0.5f);
+  const float y = fmaf(v, (float)h, -0.5f);
+  const float fx = floorf(x), fy = floorf(y);
+  const float ax = x - fx, ay = y - fy;
+  int x0 = (int)fx, y0 = (int)fy;
+  x0 = x0 < 0 ? x0 + w : x0;
+  int x1 = x0 + 1 >= w ? x0 + 1 - w : x0 + 1;
+  x0 = min(max(x0, 0), w - 1);
+  x1 = min(max(x1, 0), w - 1);
+  const int y1 = min(max(y0 + 1, 0), h - 1);
+  y0 = min(max(y0, 0), h - 1);
+  const float4 t00 = s.sky[y0 * w + x0], t10 = s.sky[y0 * w + x1];
+  const float4 t01 = s.sky[y1 * w + x0], t11 = s.sky[y1 * w + x1];
+  const float bx = 1.0f - ax, by = 1.0f - ay;
+  r = by * (bx * t00.x + ax * t10.x) + ay * (bx * t01.x + ax * t11.x);
+  g = by * (bx * t00.y + ax * t10.y) + ay * (bx * t01.y + ax * t11.y);
+  b = by * (bx * t00.z + ax * t10.z) + ay * (bx * t01.z + ax * t11.z);
+}
+
+// What a ray that leaves the scene shows.  PlainBackground: the scene's
+// background colour.  SkyBackground: the skybox where the scene has one
+// (else the background colour); a separate instantiation, so that scenes
+// without a skybox keep the kernel that has no texture lookup in it.
+struct PlainBackground {
+  __device__ __forceinline__ void colour(const SceneDev& s, const Ray&, float& r, float& g,
+                                         float& b) const {
+    r = s.bg_r; g = s.bg_g; b = s.bg_b;
+  }
+};
+struct SkyBackground {
+  __device__ __forceinline__ void colour(const SceneDev& s, const Ray& ray, float& r, float& g,
+                                         float& b) const {
+    if (s.sky) {
+      sky_colour(s, ray.dx, ray.dy, ray.dz, r, g, b);
+    } else {
+      r = s.bg_r; g = s.bg_g; b = s.bg_b;
+    }
+  }
+};
+
 // No-op sink: plain forward rendering.
 struct NoRecords {
   __device__ __forceinline__ void seg(int, int) {}
@@ -1136,7 +1193,8 @@ struct PathState {
 // `alive` says whether the path goes on (a hit below the bounce limit).
 // `sink.seg(k, id)` / `sink.lit(k, mask)` see the segment.  Every kernel runs
 // a segment through this one function, with all lanes of the wave executing.
-template <bool kFromEye, bool kPrefilter, class Sink, class Cnt, class Shadows = HardShadows>
+template <bool kFromEye, bool kPrefilter, class Sink, class Cnt, class Shadows = HardShadows,
+          class Bg = PlainBackground>
 __device__ __forceinline__ int trace_segment(const SceneDev& s, PathState& ps, int k, int depth,
                                              bool& alive, Sink& sink, Cnt& cnt,
                                              const Shadows& sh = Shadows()) {
@@ -1151,9 +1209,11 @@ __device__ __forceinline__ int trace_segment(const SceneDev& s, PathState& ps, i
     cnt.tests(s.n_spheres, s.n_planes);
     sink.seg(k, id);
     if (id < 0) {
-      ps.cr = fmaf(ps.T, s.bg_r, ps.cr);
-      ps.cg = fmaf(ps.T, s.bg_g, ps.cg);
-      ps.cb = fmaf(ps.T, s.bg_b, ps.cb);
+      float br, bg, bb;
+      Bg().colour(s, ps.r, br, bg, bb);
+      ps.cr = fmaf(ps.T, br, ps.cr);
+      ps.cg = fmaf(ps.T, bg, ps.cg);
+      ps.cb = fmaf(ps.T, bb, ps.cb);
     }
   }
   const bool hit = alive && id >= 0;
@@ -1190,7 +1250,8 @@ __device__ __forceinline__ int trace_segment(const SceneDev& s, PathState& ps, i
 // executes the segment code together.  `sink.seg(k, id)` and
 // `sink.lit(k, mask)` see every traced segment; the caller marks untraced
 // segments.  Returns the number of segments traced (0 when not live).
-template <class Sink, class Cnt = NoCount, bool kPrefilter = true, class Shadows = HardShadows>
+template <class Sink, class Cnt = NoCount, bool kPrefilter = true, class Shadows = HardShadows,
+          class Bg = PlainBackground>
 __device__ __forceinline__ int trace_path(const SceneDev& s, Ray r, int depth, bool live,
                                           float& cr, float& cg, float& cb, int& prim, Sink& sink,
                                           Cnt&& cnt = Cnt(), const Shadows& sh = Shadows()) {
@@ -1200,12 +1261,14 @@ __device__ __forceinline__ int trace_path(const SceneDev& s, Ray r, int depth, b
   ps.cr = 0.0f; ps.cg = 0.0f; ps.cb = 0.0f;
   ps.from_plane = -1;
   bool alive = live;
-  prim = trace_segment<true, kPrefilter>(s, ps, 0, depth, alive, sink, cnt, sh);
+  prim = trace_segment<true, kPrefilter, Sink, Cnt, Shadows, Bg>(s, ps, 0, depth, alive, sink,
+                                                                    cnt, sh);
   int traced = live ? 1 : 0;
   for (int k = 1; k <= depth; ++k) {
     if (!wave_any(alive)) break;
     traced = alive ? k + 1 : traced;
-    trace_segment<false, kPrefilter>(s, ps, k, depth, alive, sink, cnt, sh);
+    trace_segment<false, kPrefilter, Sink, Cnt, Shadows, Bg>(s, ps, k, depth, alive, sink, cnt,
+                                                             sh);
   }
   cr = ps.cr; cg = ps.cg; cb = ps.cb;
   return traced;

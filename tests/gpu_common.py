@@ -27,9 +27,11 @@ def log(*a):
     sys.stdout.flush()
 
 
-def gpu_render(rt, scene, cam, W, H, D, records=False):
+def gpu_render(rt, scene, cam, W, H, D, records=False, sky=None):
     h = rt.SceneHandle(scene)
     try:
+        if sky is not None:
+            rt.rt_scene_set_sky(h.handle, sky)
         rgb, ids, rec = rt.render(h.handle, cam, W, H, D, ids=True, records=records)
         torch.cuda.synchronize()
         out = dict(rgb=rgb.cpu().numpy().reshape(-1, 3).astype(np.float64),
@@ -43,12 +45,14 @@ def gpu_render(rt, scene, cam, W, H, D, records=False):
 
 
 def compare(oracle, scene, cam, W, H, D, gpu, pixels=None, label="", samples=1,
-            light_radius=0.0):
+            light_radius=0.0, sky=None):
     """Returns a stats dict; raises AssertionError when the parity bar fails.
-    samples > 1 compares soft shadows of lights of radius light_radius."""
-    base = oracle.render(scene, cam, W, H, D, pixels, samples=samples, light_radius=light_radius)
+    samples > 1 compares soft shadows of lights of radius light_radius; `sky`
+    is the skybox [h, w, 3] both sides render with."""
+    base = oracle.render(scene, cam, W, H, D, pixels, samples=samples, light_radius=light_radius,
+                         sky=sky)
     ok_cond = oracle.condition(scene, cam, W, H, D, pixels, base=base, samples=samples,
-                               light_radius=light_radius)
+                               light_radius=light_radius, sky=sky)
     sel = base.pixels
     g_rgb = gpu["rgb"][sel]
     g_ids = gpu["ids"][sel]

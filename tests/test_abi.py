@@ -145,6 +145,25 @@ def test_render_rejects_null_buffers_and_short_records(rt):
     assert rt._lib.rt_render_counts(FAKE_SCENE, C.byref(c), 8, 8, 1, None, None) == 1
 
 
+def test_set_sky_rejects_bad_arguments_before_any_device_call(rt):
+    sky = np.ones((4, 8, 3), np.float32)
+    p = sky.ctypes.data
+    f = rt._lib.rt_scene_set_sky
+    assert f(None, p, 8, 4, 0, None) == rt.RT_ERR_INVALID_ARG
+    for w, h in ((0, 4), (8, 0), (-1, 4), (rt.RT_MAX_SKY_DIM + 1, 1), (1, rt.RT_MAX_SKY_DIM + 1)):
+        assert f(FAKE_SCENE, p, w, h, 0, None) == rt.RT_ERR_INVALID_ARG, (w, h)
+    assert f(FAKE_SCENE, None, 8, 4, 0, None) == rt.RT_ERR_INVALID_ARG
+    assert f(FAKE_SCENE, None, 0, 4, 0, None) == rt.RT_ERR_INVALID_ARG
+    assert f(FAKE_SCENE, p, 8, 4, 7, None) == rt.RT_ERR_INVALID_ARG
+    for bad in (np.nan, np.inf, -np.inf):
+        s = sky.copy()
+        s[3, 7, 2] = bad
+        assert f(FAKE_SCENE, s.ctypes.data, 8, 4, 0, None) == rt.RT_ERR_INVALID_ARG
+        assert "non-finite" in rt.rt_last_error()
+    with pytest.raises(ValueError):
+        rt.rt_scene_set_sky(FAKE_SCENE, np.ones((4, 8), np.float32))
+
+
 def test_destroy_null_is_a_no_op(rt):
     assert rt._lib.rt_scene_destroy(None) == 0
 

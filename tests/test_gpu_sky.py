@@ -1,0 +1,224 @@
+"""Skybox (rt_scene_set_sky) on the GPU, against the FP64 oracle.
+
+Parity bar as for the plain background (tests/gpu_common.py): primary ids
+bit-exact off grazing pixels and colour within 1e-4 on pixels the oracle's
+jittered re-traces classify as well conditioned.  A re-trace moves every
+ray's direction, so pixels whose sky colour changes quickly with direction
+(the sun's rim) show a colour spread and are set aside.  The maps below
+include non-power-of-two sizes and cameras that look across the seam
+(directions along +z) and up towards the pole, so that the wrap in u and the
+clamp in v are both exercised."""
+
+import numpy as np
+import pytest
+import torch
+
+import scenegen
+from scenegen import Camera
+
+from .gpu_common import compare, gpu_render, log
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rt():
+    assert torch.cuda.is_available(), "GPU test without a GPU"
+    import paper_2305_07450_amd as rt
+    return rt
+
+
+def render(rt, h, cam, W, H, D, flags=0, samples=1, radius=0.0):
+    rgb = torch.empty((H, W, 3), device="cuda")
+    ids = torch.empty((H, W), dtype=torch.int32, device="cuda")
+    if samples > 1:
+        rt.rt_render_soft(h.handle, cam, W, H, D, samples, radius, rgb, ids, flags)
+    else:
+        rt.rt_render_ex(h.handle, cam, W, H, D, rgb, ids, None, flags)
+    torch.cuda.synchronize()
+    return rgb.cpu(), ids.cpu()
+
+
+SKY_CASES = [
+    # (seed, map w, h, camera yaw, pitch, fov, depth)
+    (0, 512, 256, 0.0, -4.0, 60.0, 2),
+    (1, 37, 19, 180.0, 10.0, 90.0, 3),     # looks along +z: across the seam
+    (2, 64, 32, 90.0, 55.0, 100.0, 1),     # up towards the pole
+    (3, 5, 3, -135.0, -20.0, 120.0, 4),    # a coarse map: bilinear weights dominate
+]
+
+
+@pytest.mark.parametrize("case", range(len(SKY_CASES)))
+def test_sky_parity_small_scenes(rt, oracle_mod, case):
+    seed, mw, mh, yaw, pitch, fov, D = SKY_CASES[case]
+    s = scenegen.tiny_scene(900 + seed, n_spheres=12, n_lights=2, spec_model=seed % 2)
+    sky = scenegen.sky_map(seed=50 + seed, w=mw, h=mh)
+    cam = Camera(yaw_deg=yaw, pitch_deg=pitch, fov_deg=fov)
+    W, H = 96, 54
+    log("case sky small", case, mw, mh, yaw, pitch, fov, D)
+    g = gpu_render(rt, s, cam, W, H, D, records=True, sky=sky)
+    stats, base = compare(oracle_mod, s, cam, W, H, D, g, label=f"sky{case}", sky=sky)
+    assert (base.prim_id < 0).any(), "no primary ray sees the sky"
+    assert stats["ill_conditioned"] < 0.1, stats
+
+
+def test_sky_parity_paper_scene(rt, oracle_mod):
+    """The paper's benchmark scene with a skybox (one light, one plane, five
+    spheres), hard shadows and one bounce, and soft shadows with 200 samples
+    and three bounces."""
+    s = scenegen.paper_scene()
+    sky = scenegen.sky_map()
+    cam = Camera()
+    W, H = 192, 108
+    for name, (n, D) in scenegen.PAPER_SETTINGS.items():
+        R = scenegen.PAPER_LIGHT_RADIUS if n > 1 else 0.0
+        log("case sky paper scene", name)
+        with rt.SceneHandle(s) as h:
+            rt.rt_scene_set_sky(h.handle, sky)
+            rgb, ids = render(rt, h, cam, W, H, D, samples=n, radius=R)
+        g = dict(rgb=rgb.numpy().reshape(-1, 3).astype(np.float64), ids=ids.numpy().reshape(-1))
+        compare(oracle_mod, s, cam, W, H, D, g, label=f"sky_paper_{name}", samples=n,
+                light_radius=R, sky=sky)
+
+
+def test_sky_full_size_sampled_rows(rt, oracle_mod):
+    """The 1920x1080 workload with a skybox, rendered whole in the benchmark's
+    launch; the oracle checks every 16th row."""
+    wl = scenegen.make_workload(1)
+    sky = scenegen.sky_map()
+    log("case sky full-size", wl.name)
+    g = gpu_render(rt, wl.scene, wl.camera, wl.W, wl.H, wl.depth, sky=sky)
+    rows = np.unique(np.concatenate([np.arange(0, wl.H, 16), [wl.H - 1]]))
+    pixels = (rows[:, None] * wl.W + np.arange(wl.W)[None, :]).reshape(-1)
+    compare(oracle_mod, wl.scene, wl.camera, wl.W, wl.H, wl.depth, g, pixels=pixels,
+            label="sky_" + wl.name, sky=sky)
+
+
+@pytest.mark.parametrize("soft", [False, True])
+def test_sky_bounds_change_no_bits(rt, soft):
+    s = scenegen.random_scene(np.random.default_rng(77), 60, 2)
+    cam = Camera(yaw_deg=150.0, pitch_deg=8.0, fov_deg=100.0)
+    W, H, D = 200, 120, 4
+    n, R = (48, 0.5) if soft else (1, 0.0)
+    log("case sky bits", soft)
+    with rt.SceneHandle(s) as h:
+        rt.rt_scene_set_sky(h.handle, scenegen.sky_map(seed=3, w=100, h=60))
+        a = render(rt, h, cam, W, H, D, 0, n, R)
+        b = render(rt, h, cam, W, H, D, rt.RT_RENDER_NO_PREFILTER, n, R)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
+def test_constant_sky_is_the_background(rt):
+    """A skybox of one colour everywhere shows what a plain background of that
+    colour shows, up to the rounding of the bilinear weights."""
+    s = scenegen.tiny_scene(31, n_spheres=15, n_lights=2)
+    cam = Camera(yaw_deg=20.0, pitch_deg=5.0, fov_deg=80.0)
+    W, H, D = 120, 80, 3
+    bg = np.array([0.3, 0.5, 0.7], np.float32)
+    s.background = tuple(float(v) for v in bg)
+    with rt.SceneHandle(s) as h:
+        plain = render(rt, h, cam, W, H, D)
+        rt.rt_scene_set_sky(h.handle, np.broadcast_to(bg, (7, 11, 3)).copy())
+        sky = render(rt, h, cam, W, H, D)
+    assert torch.equal(plain[1], sky[1])
+    assert (plain[1] < 0).any()
+    torch.testing.assert_close(sky[0], plain[0], rtol=1e-6, atol=1e-7)
+
+
+def test_device_upload_replace_and_remove(rt):
+    """A map from device memory renders the same bits as the same map from
+    host memory; a map replaced in place, or with another size, renders as a
+    fresh upload of it; removing it brings back the plain background."""
+    s = scenegen.tiny_scene(32, n_spheres=10, n_lights=1)
+    cam = Camera(yaw_deg=170.0, pitch_deg=20.0, fov_deg=90.0)
+    W, H, D = 90, 60, 2
+    a = scenegen.sky_map(seed=5, w=64, h=32)
+    b = scenegen.sky_map(seed=6, w=64, h=32)
+    c = scenegen.sky_map(seed=7, w=48, h=24)
+    with rt.SceneHandle(s) as h:
+        plain = render(rt, h, cam, W, H, D)
+        rt.rt_scene_set_sky(h.handle, a)
+        host_a = render(rt, h, cam, W, H, D)
+        keep = rt.rt_scene_set_sky(h.handle, torch.from_numpy(a).cuda())
+        dev_a = render(rt, h, cam, W, H, D)
+        del keep
+        rt.rt_scene_set_sky(h.handle, b)
+        in_place_b = render(rt, h, cam, W, H, D)
+        rt.rt_scene_set_sky(h.handle, c)
+        resized_c = render(rt, h, cam, W, H, D)
+        rt.rt_scene_set_sky(h.handle, None)
+        removed = render(rt, h, cam, W, H, D)
+    for m, want in ((b, in_place_b), (c, resized_c)):
+        with rt.SceneHandle(s) as h:
+            rt.rt_scene_set_sky(h.handle, m)
+            fresh = render(rt, h, cam, W, H, D)
+        assert torch.equal(fresh[0], want[0])
+    assert torch.equal(host_a[0], dev_a[0]) and torch.equal(host_a[1], dev_a[1])
+    assert not torch.equal(host_a[0], in_place_b[0])
+    assert torch.equal(removed[0], plain[0]) and torch.equal(removed[1], plain[1])
+
+
+def test_batch_with_skies_bit_exact_and_stale_sky_refused(rt):
+    """A batch that mixes scenes with and without a skybox renders every image
+    as rt_render does; a skybox resized or removed after the batch was made
+    makes the launch fail, one replaced at its size does not."""
+    specs = [(64, 36, 2, 5, 1, True), (37, 23, 0, 3, 2, False), (130, 70, 4, 40, 1, True),
+             (16, 100, 1, 9, 3, False), (96, 54, 3, 0, 1, True)]
+    wls, skies = [], []
+    for i, (W, H, D, N, L, with_sky) in enumerate(specs):
+        s = scenegen.tiny_scene(60 + i, n_spheres=N, n_lights=L, spec_model=i % 2)
+        cam = Camera(yaw_deg=40.0 * i, pitch_deg=6.0, fov_deg=70.0 + 5 * i)
+        wls.append(scenegen.Workload(f"s{i}", s, cam, W, H, D))
+        skies.append(scenegen.sky_map(seed=20 + i, w=32 + 8 * i, h=16 + 4 * i) if with_sky
+                     else None)
+    handles = [rt.SceneHandle(w.scene) for w in wls]
+    try:
+        for h, sky in zip(handles, skies):
+            if sky is not None:
+                rt.rt_scene_set_sky(h.handle, sky)
+        ref = []
+        for wl, h in zip(wls, handles):
+            ref.append(render(rt, h, wl.camera, wl.W, wl.H, wl.depth)[0])
+        outs = [torch.full((wl.H, wl.W, 3), float("nan"), device="cuda") for wl in wls]
+        b = rt.rt_batch_create([h.handle for h in handles], [w.camera for w in wls],
+                               [w.W for w in wls], [w.H for w in wls], [w.depth for w in wls],
+                               outs, autotune=False)
+        try:
+            for direct in (False, True):
+                for o in outs:
+                    o.fill_(float("nan"))
+                (rt.rt_batch_launch_direct if direct else rt.rt_batch_launch)(b)
+                torch.cuda.synchronize()
+                for i, (o, r) in enumerate(zip(outs, ref)):
+                    assert torch.equal(o.cpu(), r), (direct, i)
+            rt.rt_scene_set_sky(handles[0].handle, scenegen.sky_map(seed=99, w=32, h=16))
+            rt.rt_batch_launch(b)
+            torch.cuda.synchronize()
+            rt.rt_scene_set_sky(handles[2].handle, scenegen.sky_map(seed=99, w=10, h=10))
+            for launch in (rt.rt_batch_launch, rt.rt_batch_launch_direct):
+                with pytest.raises(rt.RtError) as e:
+                    launch(b)
+                assert e.value.status == rt.RT_ERR_INVALID_ARG
+                assert "skybox of scene 2" in rt.rt_last_error()
+        finally:
+            rt.rt_batch_destroy(b)
+    finally:
+        for h in handles:
+            h.close()
+
+
+def test_backward_refuses_a_sky(rt):
+    s = scenegen.tiny_scene(33, n_spheres=4, n_lights=1)
+    cam = Camera()
+    W, H, D = 32, 24, 1
+    g = torch.ones((H, W, 3), device="cuda")
+    grads = {"albedo": torch.empty((4, 3), device="cuda")}
+    with rt.SceneHandle(s) as h:
+        rt.rt_scene_set_sky(h.handle, scenegen.sky_map(w=16, h=8))
+        with pytest.raises(rt.RtError) as e:
+            rt.rt_render_backward(h.handle, cam, W, H, D, g, grads)
+        assert e.value.status == rt.RT_ERR_UNSUPPORTED
+        rt.rt_scene_set_sky(h.handle, None)
+        rt.rt_render_backward(h.handle, cam, W, H, D, g, grads)
+        torch.cuda.synchronize()
+        assert torch.isfinite(grads["albedo"]).all()
