@@ -218,6 +218,50 @@ def bench_paper_scene(rt, scenegen, stream, reps=10):
     return out
 
 
+def bench_interactive(rt, scenegen, stream, frames=60):
+    """The paper's interactive loop (its GUI runs, minus the GUI): every frame
+    streams new sphere centres (a Verlet step of the five bodies) and a moving
+    camera in, renders the paper-scene stand-in with its skybox, and streams
+    the image out to pinned host memory (rt_frame_*); frame k+1 is submitted
+    before frame k is taken.  Host wall clock per frame, both settings, 720p,
+    1080p and 4K."""
+    import time
+    s = scenegen.paper_scene()
+    warm = 4
+    motion = scenegen.verlet_motion(s, frames + warm)
+    h = rt.SceneHandle(s)
+    rt.rt_scene_set_sky(h.handle, scenegen.sky_map())
+    out = {"frames": frames, "skybox": "procedural 512x256",
+           "motion": "Verlet step of 5 spheres per frame, 1/60 s", "stream_out": "float32 RGB"}
+    R = scenegen.PAPER_LIGHT_RADIUS
+    for name, (n, D) in scenegen.PAPER_SETTINGS.items():
+        soft = n > 1
+        res = {}
+        for W, H in PAPER_SIZES:
+            img = torch_empty_image(H, W)
+            f = rt.rt_frame_create(h.handle, W, H, img, soft=soft, stream_out=True)
+
+            def run(k0, count):
+                def cam(k):
+                    return scenegen.Camera(yaw_deg=-10.0 + 0.3 * k, pitch_deg=-3.0)
+                rt.rt_frame_submit(f, cam(k0), D, n, R if soft else 0.0, motion[k0], stream)
+                for k in range(k0 + 1, k0 + count):
+                    rt.rt_frame_submit(f, cam(k), D, n, R if soft else 0.0, motion[k], stream)
+                    rt.rt_frame_result(f, W, H)
+                rt.rt_frame_result(f, W, H)
+
+            run(0, warm)
+            t0 = time.perf_counter()
+            run(warm, frames)
+            ms = (time.perf_counter() - t0) * 1e3 / frames
+            rt.rt_frame_destroy(f)
+            res[f"{W}x{H}"] = {"ms": round(ms, 4), "fps": round(1e3 / ms, 1),
+                               "image_MB": round(W * H * 12 / 1e6, 2)}
+        out[name] = {"samples": n, "depth": D, **res}
+    h.close()
+    return out
+
+
 def torch_empty_image(H, W):
     import torch
     return torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
@@ -335,6 +379,7 @@ def main():
         out["batch"] = bench_batch(rt, scenegen, stream, 10)
         out["other_workloads"] = bench_configs(rt, scenegen, stream)
         out["paper_scene"] = bench_paper_scene(rt, scenegen, stream)
+        out["interactive"] = bench_interactive(rt, scenegen, stream)
         out["paper_context"] = PAPER_CONTEXT
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)

@@ -260,6 +260,61 @@ rt_status rt_batch_shape(rt_batch batch, int32_t* workgroups, int32_t* tile_w, i
 
 rt_status rt_batch_destroy(rt_batch batch);
 
+/* ---- Interactive per-frame path ------------------------------------------
+ * The paper's GUI loop streams the camera, the ray-tracing properties (shadow
+ * samples, bounce limit) and the body positions in for every frame, renders,
+ * and streams the pixels out (Section 3.9, its task schedule).  A frame object
+ * holds that loop for one scene and one image size as a HIP graph replayed
+ * once per frame with new node parameters: positions host -> device, one
+ * kernel that moves the spheres and rebuilds their light and eye cones, the
+ * render (rt_render_ex's or rt_render_soft's kernel), and optionally the image
+ * device -> host.  Two slots alternate, so the host can stage frame k+1 while
+ * the device renders frame k.  Each frame's image is bit-identical to
+ * rt_scene_update (same centres) followed by rt_render_ex / rt_render_soft. */
+typedef struct rt_frame_s* rt_frame;
+
+typedef struct {
+  int32_t W, H;         /* image size, 1 .. RT_MAX_DIM                          */
+  int32_t soft;         /* 0: hard shadows (rt_render_ex), 1: soft (rt_render_soft) */
+  int32_t stream_out;   /* non-zero: copy every image to library-owned pinned host
+                           memory (rt_frame_result)                              */
+  uint32_t flags;       /* RT_RENDER_* as rt_render_ex                          */
+  float* rgb_out;       /* device float32 [H][W][3], caller-owned               */
+} rt_frame_desc;
+
+typedef struct {
+  rt_camera cam;
+  int32_t depth;            /* bounce limit, 0 .. RT_MAX_DEPTH                  */
+  int32_t samples;          /* hard frames: 1; soft frames: 2 .. RT_MAX_SAMPLES */
+  float light_radius;       /* soft frames: finite, > 0; hard frames: unused    */
+  const float* sphere_pos;  /* host float32 [N][3] new sphere centres (radii and
+                               everything else stay), or NULL to keep them      */
+} rt_frame_input;
+
+/* Allocates the device position buffer, two pinned staging and (stream_out)
+ * two pinned image copies, and builds the two graphs; not capture-safe.  The
+ * scene must outlive the frame and keep its counts. */
+rt_status rt_frame_create(rt_scene scene, const rt_frame_desc* desc, rt_frame* out);
+
+/* Stage one frame and launch its graph on `stream` (every frame of one frame
+ * object on the same stream).  Copies sphere_pos into the slot's pinned
+ * staging before it returns, after waiting for the frame that used the slot
+ * two submits ago.  Moving the spheres changes the scene itself, as
+ * rt_scene_update does.  A skybox added or removed since the last frame
+ * rebuilds the graphs (allocates); otherwise no allocation. */
+rt_status rt_frame_submit(rt_frame frame, const rt_frame_input* in, void* stream);
+
+/* Wait for the oldest submitted frame not yet returned, in submission order
+ * (a submit that finds two frames not yet returned drops the older one, so
+ * an interactive loop may submit frame k+1 before it takes frame k).  With
+ * stream_out, *host_rgb (may be NULL) points at that frame's image, float32
+ * [H][W][3], valid until the second rt_frame_submit after the frame's own;
+ * else *host_rgb is NULL.  RT_ERR_INVALID_ARG when no frame is waiting. */
+rt_status rt_frame_result(rt_frame frame, const float** host_rgb);
+
+/* Waits for the frame's work, then frees it. */
+rt_status rt_frame_destroy(rt_frame frame);
+
 const char* rt_status_string(rt_status status);
 const char* rt_last_error(void);
 

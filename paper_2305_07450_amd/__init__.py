@@ -29,6 +29,7 @@ RT_MAX_PLANES = 16
 RT_RENDER_NO_PREFILTER = 1
 RT_MAX_SAMPLES = 4096
 RT_MAX_SKY_DIM = 16384
+RT_MAX_DIM = 16384
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(
@@ -66,6 +67,16 @@ class rt_grads(C.Structure):
                 ("d_light_pos", C.c_void_p), ("d_light_int", C.c_void_p)]
 
 
+class rt_frame_desc(C.Structure):
+    _fields_ = [("W", C.c_int32), ("H", C.c_int32), ("soft", C.c_int32),
+                ("stream_out", C.c_int32), ("flags", C.c_uint32), ("rgb_out", C.c_void_p)]
+
+
+class rt_frame_input(C.Structure):
+    _fields_ = [("cam", rt_camera), ("depth", C.c_int32), ("samples", C.c_int32),
+                ("light_radius", C.c_float), ("sphere_pos", C.c_void_p)]
+
+
 _lib = C.CDLL(LIB_PATH)
 _vp = C.c_void_p
 _i32 = C.c_int32
@@ -91,6 +102,10 @@ _sig = {
     "rt_batch_launch_direct": (C.c_int, [_vp, _vp]),
     "rt_batch_shape": (C.c_int, [_vp, C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_i32)]),
     "rt_batch_destroy": (C.c_int, [_vp]),
+    "rt_frame_create": (C.c_int, [_vp, C.POINTER(rt_frame_desc), C.POINTER(_vp)]),
+    "rt_frame_submit": (C.c_int, [_vp, C.POINTER(rt_frame_input), _vp]),
+    "rt_frame_result": (C.c_int, [_vp, C.POINTER(C.POINTER(C.c_float))]),
+    "rt_frame_destroy": (C.c_int, [_vp]),
     "rt_status_string": (C.c_char_p, [C.c_int]),
     "rt_last_error": (C.c_char_p, []),
 }
@@ -309,6 +324,44 @@ def rt_batch_shape(batch: int):
 
 def rt_batch_destroy(batch: int):
     _check(_lib.rt_batch_destroy(batch))
+
+
+def rt_frame_create(handle: int, W: int, H: int, rgb_out: torch.Tensor, soft: bool = False,
+                    stream_out: bool = False, flags: int = 0) -> int:
+    """Interactive per-frame path for one scene and image size (see
+    include/rt.h); rgb_out is the device image every frame renders into."""
+    d = rt_frame_desc(int(W), int(H), int(bool(soft)), int(bool(stream_out)), int(flags),
+                      _ptr(rgb_out))
+    f = _vp()
+    _check(_lib.rt_frame_create(handle, C.byref(d), C.byref(f)))
+    return f.value
+
+
+def rt_frame_submit(frame: int, camera, depth: int, samples: int = 1, light_radius: float = 0.0,
+                    sphere_pos=None, stream=None):
+    """Stage and launch one frame; sphere_pos is a host float32 [N, 3] array of
+    new centres, or None to keep them."""
+    pos = None
+    if sphere_pos is not None:
+        pos = np.ascontiguousarray(sphere_pos, dtype=np.float32)
+    inp = rt_frame_input(make_camera(camera), int(depth), int(samples), float(light_radius),
+                         _ptr(pos) if pos is not None else None)
+    _check(_lib.rt_frame_submit(frame, C.byref(inp), _stream(stream)))
+
+
+def rt_frame_result(frame: int, W: int = 0, H: int = 0):
+    """Wait for the oldest frame not yet returned.  With stream_out, returns a
+    numpy view [H, W, 3] of its pinned host image (valid until the second
+    submit after the frame's own); otherwise None."""
+    p = C.POINTER(C.c_float)()
+    _check(_lib.rt_frame_result(frame, C.byref(p)))
+    if not p:
+        return None
+    return np.ctypeslib.as_array(p, shape=(int(H), int(W), 3))
+
+
+def rt_frame_destroy(frame: int):
+    _check(_lib.rt_frame_destroy(frame))
 
 
 # ---------------------------------------------------------------- helpers

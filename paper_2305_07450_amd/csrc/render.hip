@@ -162,6 +162,24 @@ hipError_t launch_counts(const SceneDev& s, const CameraDev& c, int depth,
   return hipGetLastError();
 }
 
+const void* render_kernel_fn(bool sky, bool prefilter) {
+  if (sky)
+    return prefilter ? (const void*)render_kernel<false, true, SkyBackground>
+                     : (const void*)render_kernel<false, false, SkyBackground>;
+  return prefilter ? (const void*)render_kernel<false, true, PlainBackground>
+                   : (const void*)render_kernel<false, false, PlainBackground>;
+}
+
+const void* render_soft_kernel_fn(bool sky, bool prefilter) {
+  if (sky)
+    return prefilter ? (const void*)render_soft_kernel<true, SkyBackground>
+                     : (const void*)render_soft_kernel<false, SkyBackground>;
+  return prefilter ? (const void*)render_soft_kernel<true, PlainBackground>
+                   : (const void*)render_soft_kernel<false, PlainBackground>;
+}
+
+const void* sample_table_kernel_fn() { return (const void*)sample_table_kernel; }
+
 hipError_t launch_render(const SceneDev& s, const CameraDev& c, int depth, float* rgb,
                          int32_t* ids, int32_t* rec_ids, uint8_t* rec_lit, bool prefilter,
                          hipStream_t stream) {

@@ -20,7 +20,7 @@ static thread_local std::string g_last_error;
 
 void set_error(const std::string& msg) { g_last_error = msg; }
 
-static rt_status fail(rt_status st, const char* fmt, ...) {
+rt_status fail(rt_status st, const char* fmt, ...) {
   char buf[512];
   va_list ap;
   va_start(ap, fmt);
@@ -67,7 +67,7 @@ CameraDev camera_dev(const rt_camera& cam, int W, int H) {
   return c;
 }
 
-static bool finite_all(const float* a, int64_t n) {
+bool finite_all(const float* a, int64_t n) {
   for (int64_t i = 0; i < n; ++i)
     if (!isfinite(a[i])) return false;
   return true;
@@ -124,7 +124,7 @@ static rt_status validate_desc(const rt_scene_desc* d) {
   return RT_OK;
 }
 
-static rt_status validate_camera(const rt_camera* cam, int32_t W, int32_t H, int32_t depth) {
+rt_status validate_camera(const rt_camera* cam, int32_t W, int32_t H, int32_t depth) {
   if (!cam) return fail(RT_ERR_INVALID_ARG, "camera is NULL");
   float v[6] = {cam->eye[0], cam->eye[1], cam->eye[2], cam->yaw_deg, cam->pitch_deg,
                 cam->fov_deg};

@@ -55,8 +55,11 @@ namespace rtk {
 constexpr int kAdjointBlocks = 1024;
 
 void set_error(const std::string& msg);
+rt_status fail(rt_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 rt_status hip_fail(hipError_t e, const char* what);
 CameraDev camera_dev(const rt_camera& cam, int W, int H);
+bool finite_all(const float* a, int64_t n);
+rt_status validate_camera(const rt_camera* cam, int32_t W, int32_t H, int32_t depth);
 
 // Raw (desc-layout) arrays the pack kernel reads.
 struct RawScene {
@@ -79,6 +82,14 @@ hipError_t launch_eye_cones(const rt_scene_s& sc, const CameraDev& c, hipStream_
 hipError_t launch_render_soft(const rt_scene_s& sc, const CameraDev& c, int depth, int samples,
                               float radius, float* rgb, int32_t* ids, bool prefilter,
                               hipStream_t stream);
+
+// The render kernels' entry addresses, for graph nodes built by hand: the
+// hard-shadow render without records, and the soft-shadow render, with or
+// without the skybox lookup and the wave bounds; the sample-table kernel.
+// Their parameters are those of the kernels in render.hip.
+const void* render_kernel_fn(bool sky, bool prefilter);
+const void* render_soft_kernel_fn(bool sky, bool prefilter);
+const void* sample_table_kernel_fn();
 
 hipError_t launch_render(const SceneDev& s, const CameraDev& c, int depth, float* rgb,
                          int32_t* ids, int32_t* rec_ids, uint8_t* rec_lit, bool prefilter,

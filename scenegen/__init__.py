@@ -278,6 +278,38 @@ def sky_map(seed: int = 38, w: int = 512, h: int = 256) -> np.ndarray:
     return np.clip(sky, 0.0, None).astype(F32)
 
 
+def verlet_motion(scene: Scene, frames: int, seed: int = 7, dt: float = 1.0 / 60.0,
+                  gravity: float = 9.81, speed: float = 2.0) -> np.ndarray:
+    """Sphere centres for `frames` frames, float32 [frames, N, 3]: the paper's
+    physics system moves its bodies by Verlet integration, and this stands in
+    for it as a driver of the per-frame position stream.  Position Verlet,
+    x_{k+1} = 2 x_k - x_{k-1} + a dt^2 with a = (0, -gravity, 0), from seeded
+    initial velocities of magnitude up to `speed`; a sphere that sinks into
+    the ground plane y = -1 is mirrored back above it (an elastic bounce;
+    one that starts sunk bounces at its starting height).
+    Frame 0 is the scene's own centres.  Host-side input generation only."""
+    rng = np.random.default_rng(seed)
+    g = np.asarray(scene.sphere_geom, dtype=np.float64).reshape(-1, 4)
+    x = g[:, :3].copy()
+    r = g[:, 3]
+    v = rng.uniform(-speed, speed, size=x.shape)
+    prev = x - v * dt
+    acc = np.array([0.0, -gravity, 0.0])
+    out = np.empty((frames, x.shape[0], 3), dtype=F32)
+    floor = np.minimum(-1.0 + r, x[:, 1])    # a sphere that starts sunk bounces there
+    for k in range(frames):
+        out[k] = x.astype(F32)
+        nxt = 2.0 * x - prev + acc * dt * dt
+        low = nxt[:, 1] < floor
+        # mirror both the new and the current height about the floor: the
+        # vertical velocity changes sign, the horizontal one stays
+        nxt[low, 1] = 2.0 * floor[low] - nxt[low, 1]
+        x_c = x.copy()
+        x_c[low, 1] = 2.0 * floor[low] - x[low, 1]
+        prev, x = x_c, nxt
+    return out
+
+
 def paper_scene(seed: int = 2305) -> Scene:
     return random_scene(np.random.default_rng(seed), 5, 1, box=PAPER_BOX, radii=PAPER_RADII)
 

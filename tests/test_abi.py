@@ -164,6 +164,25 @@ def test_set_sky_rejects_bad_arguments_before_any_device_call(rt):
         rt.rt_scene_set_sky(FAKE_SCENE, np.ones((4, 8), np.float32))
 
 
+def test_frame_rejects_bad_arguments_before_any_device_call(rt):
+    good = dict(W=8, H=8, soft=0, stream_out=0, flags=0, rgb_out=0x1000)
+    f = C.c_void_p()
+    for field, val in (("W", 0), ("H", -1), ("W", rt.RT_MAX_DIM + 1), ("soft", 2), ("flags", 4),
+                       ("rgb_out", None)):
+        d = rt.rt_frame_desc(**{**good, field: val})
+        assert rt._lib.rt_frame_create(FAKE_SCENE, C.byref(d), C.byref(f)) == 1, field
+        assert not f.value
+    d = rt.rt_frame_desc(**good)
+    assert rt._lib.rt_frame_create(None, C.byref(d), C.byref(f)) == 1
+    assert rt._lib.rt_frame_create(FAKE_SCENE, None, C.byref(f)) == 1
+    assert rt._lib.rt_frame_create(FAKE_SCENE, C.byref(d), None) == 1
+    inp = rt.rt_frame_input(rt.make_camera(Camera()), 1, 1, 0.0, None)
+    assert rt._lib.rt_frame_submit(None, C.byref(inp), None) == 1
+    assert rt._lib.rt_frame_submit(FAKE_SCENE, None, None) == 1
+    assert rt._lib.rt_frame_result(None, None) == 1
+    assert rt._lib.rt_frame_destroy(None) == 0
+
+
 def test_destroy_null_is_a_no_op(rt):
     assert rt._lib.rt_scene_destroy(None) == 0
 
