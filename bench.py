@@ -224,7 +224,8 @@ def bench_interactive(rt, scenegen, stream, frames=60):
     camera in, renders the paper-scene stand-in with its skybox, and streams
     the image out to pinned host memory (rt_frame_*); frame k+1 is submitted
     before frame k is taken.  Host wall clock per frame, both settings, 720p,
-    1080p and 4K."""
+    1080p and 4K, with the paper's 32-bit pixels (packed on the device) and
+    with the float image."""
     import time
     s = scenegen.paper_scene()
     warm = 4
@@ -232,31 +233,34 @@ def bench_interactive(rt, scenegen, stream, frames=60):
     h = rt.SceneHandle(s)
     rt.rt_scene_set_sky(h.handle, scenegen.sky_map())
     out = {"frames": frames, "skybox": "procedural 512x256",
-           "motion": "Verlet step of 5 spheres per frame, 1/60 s", "stream_out": "float32 RGB"}
+           "motion": "Verlet step of 5 spheres per frame, 1/60 s"}
     R = scenegen.PAPER_LIGHT_RADIUS
     for name, (n, D) in scenegen.PAPER_SETTINGS.items():
         soft = n > 1
         res = {}
-        for W, H in PAPER_SIZES:
-            img = torch_empty_image(H, W)
-            f = rt.rt_frame_create(h.handle, W, H, img, soft=soft, stream_out=True)
+        for fmt, fmt_name, bpp in ((rt.RT_FRAME_ARGB8, "argb8", 4),
+                                   (rt.RT_FRAME_RGB32F, "rgb32f", 12)):
+            for W, H in PAPER_SIZES:
+                img = torch_empty_image(H, W)
+                f = rt.rt_frame_create(h.handle, W, H, img, soft=soft, stream_out=True, fmt=fmt)
 
-            def run(k0, count):
-                def cam(k):
-                    return scenegen.Camera(yaw_deg=-10.0 + 0.3 * k, pitch_deg=-3.0)
-                rt.rt_frame_submit(f, cam(k0), D, n, R if soft else 0.0, motion[k0], stream)
-                for k in range(k0 + 1, k0 + count):
-                    rt.rt_frame_submit(f, cam(k), D, n, R if soft else 0.0, motion[k], stream)
-                    rt.rt_frame_result(f, W, H)
-                rt.rt_frame_result(f, W, H)
+                def run(k0, count):
+                    def cam(k):
+                        return scenegen.Camera(yaw_deg=-10.0 + 0.3 * k, pitch_deg=-3.0)
+                    rad = R if soft else 0.0
+                    rt.rt_frame_submit(f, cam(k0), D, n, rad, motion[k0], stream)
+                    for k in range(k0 + 1, k0 + count):
+                        rt.rt_frame_submit(f, cam(k), D, n, rad, motion[k], stream)
+                        rt.rt_frame_result(f)
+                    rt.rt_frame_result(f)
 
-            run(0, warm)
-            t0 = time.perf_counter()
-            run(warm, frames)
-            ms = (time.perf_counter() - t0) * 1e3 / frames
-            rt.rt_frame_destroy(f)
-            res[f"{W}x{H}"] = {"ms": round(ms, 4), "fps": round(1e3 / ms, 1),
-                               "image_MB": round(W * H * 12 / 1e6, 2)}
+                run(0, warm)
+                t0 = time.perf_counter()
+                run(warm, frames)
+                ms = (time.perf_counter() - t0) * 1e3 / frames
+                rt.rt_frame_destroy(f)
+                res[f"{fmt_name}_{W}x{H}"] = {"ms": round(ms, 4), "fps": round(1e3 / ms, 1),
+                                             "stream_out_MB": round(W * H * bpp / 1e6, 2)}
         out[name] = {"samples": n, "depth": D, **res}
     h.close()
     return out

@@ -270,14 +270,24 @@ rt_status rt_batch_destroy(rt_batch batch);
  * render (rt_render_ex's or rt_render_soft's kernel), and optionally the image
  * device -> host.  Two slots alternate, so the host can stage frame k+1 while
  * the device renders frame k.  Each frame's image is bit-identical to
- * rt_scene_update (same centres) followed by rt_render_ex / rt_render_soft. */
+ * rt_scene_update (same centres) followed by rt_render_ex / rt_render_soft.
+ *
+ * Streamed-out formats: RT_FRAME_RGB32F, the float image itself;
+ * RT_FRAME_ARGB8, the paper's integer pixels (one uint32 per pixel, alpha 255
+ * in the top byte, then red, green, blue; each channel
+ * floor(clamp(c, 0, 1) * 255 + 0.5) with the product and the sum rounded to
+ * FP32), a third of the bytes, packed on the device before the copy. */
 typedef struct rt_frame_s* rt_frame;
+
+typedef enum { RT_FRAME_RGB32F = 0, RT_FRAME_ARGB8 = 1 } rt_frame_format;
 
 typedef struct {
   int32_t W, H;         /* image size, 1 .. RT_MAX_DIM                          */
   int32_t soft;         /* 0: hard shadows (rt_render_ex), 1: soft (rt_render_soft) */
   int32_t stream_out;   /* non-zero: copy every image to library-owned pinned host
                            memory (rt_frame_result)                              */
+  int32_t format;       /* rt_frame_format of the streamed-out image; ARGB8 needs
+                           stream_out                                            */
   uint32_t flags;       /* RT_RENDER_* as rt_render_ex                          */
   float* rgb_out;       /* device float32 [H][W][3], caller-owned               */
 } rt_frame_desc;
@@ -292,8 +302,9 @@ typedef struct {
 } rt_frame_input;
 
 /* Allocates the device position buffer, two pinned staging and (stream_out)
- * two pinned image copies, and builds the two graphs; not capture-safe.  The
- * scene must outlive the frame and keep its counts. */
+ * two pinned image copies, for ARGB8 a device pixel buffer, and builds the
+ * two graphs; not capture-safe.  The scene must outlive the frame and keep
+ * its counts. */
 rt_status rt_frame_create(rt_scene scene, const rt_frame_desc* desc, rt_frame* out);
 
 /* Stage one frame and launch its graph on `stream` (every frame of one frame
@@ -307,10 +318,11 @@ rt_status rt_frame_submit(rt_frame frame, const rt_frame_input* in, void* stream
 /* Wait for the oldest submitted frame not yet returned, in submission order
  * (a submit that finds two frames not yet returned drops the older one, so
  * an interactive loop may submit frame k+1 before it takes frame k).  With
- * stream_out, *host_rgb (may be NULL) points at that frame's image, float32
- * [H][W][3], valid until the second rt_frame_submit after the frame's own;
- * else *host_rgb is NULL.  RT_ERR_INVALID_ARG when no frame is waiting. */
-rt_status rt_frame_result(rt_frame frame, const float** host_rgb);
+ * stream_out, *host_image (may be NULL) points at that frame's image, float32
+ * [H][W][3] or uint32 [H][W] per the format, valid until the second
+ * rt_frame_submit after the frame's own; else *host_image is NULL.
+ * RT_ERR_INVALID_ARG when no frame is waiting. */
+rt_status rt_frame_result(rt_frame frame, const void** host_image);
 
 /* Waits for the frame's work, then frees it. */
 rt_status rt_frame_destroy(rt_frame frame);

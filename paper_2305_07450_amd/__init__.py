@@ -30,6 +30,7 @@ RT_RENDER_NO_PREFILTER = 1
 RT_MAX_SAMPLES = 4096
 RT_MAX_SKY_DIM = 16384
 RT_MAX_DIM = 16384
+RT_FRAME_RGB32F, RT_FRAME_ARGB8 = 0, 1
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(
@@ -69,7 +70,8 @@ class rt_grads(C.Structure):
 
 class rt_frame_desc(C.Structure):
     _fields_ = [("W", C.c_int32), ("H", C.c_int32), ("soft", C.c_int32),
-                ("stream_out", C.c_int32), ("flags", C.c_uint32), ("rgb_out", C.c_void_p)]
+                ("stream_out", C.c_int32), ("format", C.c_int32), ("flags", C.c_uint32),
+                ("rgb_out", C.c_void_p)]
 
 
 class rt_frame_input(C.Structure):
@@ -104,7 +106,7 @@ _sig = {
     "rt_batch_destroy": (C.c_int, [_vp]),
     "rt_frame_create": (C.c_int, [_vp, C.POINTER(rt_frame_desc), C.POINTER(_vp)]),
     "rt_frame_submit": (C.c_int, [_vp, C.POINTER(rt_frame_input), _vp]),
-    "rt_frame_result": (C.c_int, [_vp, C.POINTER(C.POINTER(C.c_float))]),
+    "rt_frame_result": (C.c_int, [_vp, C.POINTER(_vp)]),
     "rt_frame_destroy": (C.c_int, [_vp]),
     "rt_status_string": (C.c_char_p, [C.c_int]),
     "rt_last_error": (C.c_char_p, []),
@@ -327,11 +329,12 @@ def rt_batch_destroy(batch: int):
 
 
 def rt_frame_create(handle: int, W: int, H: int, rgb_out: torch.Tensor, soft: bool = False,
-                    stream_out: bool = False, flags: int = 0) -> int:
+                    stream_out: bool = False, fmt: int = 0, flags: int = 0) -> int:
     """Interactive per-frame path for one scene and image size (see
-    include/rt.h); rgb_out is the device image every frame renders into."""
-    d = rt_frame_desc(int(W), int(H), int(bool(soft)), int(bool(stream_out)), int(flags),
-                      _ptr(rgb_out))
+    include/rt.h); rgb_out is the device image every frame renders into, fmt
+    the streamed-out format (RT_FRAME_RGB32F or RT_FRAME_ARGB8)."""
+    d = rt_frame_desc(int(W), int(H), int(bool(soft)), int(bool(stream_out)), int(fmt),
+                      int(flags), _ptr(rgb_out))
     f = _vp()
     _check(_lib.rt_frame_create(handle, C.byref(d), C.byref(f)))
     return f.value
@@ -349,15 +352,18 @@ def rt_frame_submit(frame: int, camera, depth: int, samples: int = 1, light_radi
     _check(_lib.rt_frame_submit(frame, C.byref(inp), _stream(stream)))
 
 
-def rt_frame_result(frame: int, W: int = 0, H: int = 0):
+def rt_frame_result(frame: int, W: int = 0, H: int = 0, fmt: int = 0):
     """Wait for the oldest frame not yet returned.  With stream_out, returns a
-    numpy view [H, W, 3] of its pinned host image (valid until the second
-    submit after the frame's own); otherwise None."""
-    p = C.POINTER(C.c_float)()
+    numpy view of its pinned host image (valid until the second submit after
+    the frame's own): float32 [H, W, 3] for RT_FRAME_RGB32F, uint32 [H, W]
+    for RT_FRAME_ARGB8; otherwise None."""
+    p = _vp()
     _check(_lib.rt_frame_result(frame, C.byref(p)))
-    if not p:
+    if not p.value:
         return None
-    return np.ctypeslib.as_array(p, shape=(int(H), int(W), 3))
+    if fmt == RT_FRAME_ARGB8:
+        return np.ctypeslib.as_array(C.cast(p, C.POINTER(C.c_uint32)), shape=(int(H), int(W)))
+    return np.ctypeslib.as_array(C.cast(p, C.POINTER(C.c_float)), shape=(int(H), int(W), 3))
 
 
 def rt_frame_destroy(frame: int):

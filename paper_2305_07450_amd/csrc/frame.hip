@@ -8,10 +8,14 @@
 // the device renders frame k:
 //   positions H2D (pinned slot staging -> device)
 //   -> prep kernel (move the spheres, rebuild their light cones and the eye cones)
-//   -> [soft frames: sample table] -> render -> [image D2H into the slot's pinned copy]
+//   -> [soft frames: sample table] -> render
+//   -> [packed pixels: pack kernel] -> [image D2H into the slot's pinned copy]
 // Graphs launched on one stream run in order, so the device-side buffers
-// (positions, the scene, the image) are shared by the slots; only the
-// host-side staging and image copies are per slot.
+// (positions, the scene, the image, the packed pixels) are shared by the
+// slots; only the host-side staging and image copies are per slot.  The
+// copy-out stays in the render's stream: run beside the device-to-host copy
+// (a copy kernel), the render kernel slowed down by about the copy's length,
+// so the overlap gained nothing.
 #include <string.h>
 
 #include <cmath>
@@ -58,6 +62,24 @@ __global__ void frame_prep_kernel(PrepArgs a) {
   }
 }
 
+// One 8-bit channel of a packed pixel: round(clamp(c, 0, 1) * 255), the
+// product and the half added in FP32 (each rounded once), then floored.  A
+// NaN clamps to 0.
+__device__ __forceinline__ uint32_t channel8(float c) {
+  const float x = fminf(fmaxf(c, 0.0f), 1.0f);
+  return (uint32_t)floorf(x * 255.0f + 0.5f);
+}
+
+// The image as 32-bit ARGB pixels (alpha 255), one lane per pixel.
+__global__ void pack_argb_kernel(const float* __restrict__ rgb, uint32_t* __restrict__ px,
+                                 int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const float r = rgb[3 * i], g = rgb[3 * i + 1], b = rgb[3 * i + 2];
+    px[i] = 0xFF000000u | (channel8(r) << 16) | (channel8(g) << 8) | channel8(b);
+  }
+}
+
 }  // namespace rtk
 
 using namespace rtk;
@@ -66,7 +88,7 @@ namespace {
 
 struct Slot {
   float* h_pos = nullptr;   // pinned [N][3]
-  float* h_rgb = nullptr;   // pinned [H][W][3] (stream_out only)
+  void* h_img = nullptr;    // pinned image copy (stream_out): float [H][W][3] or uint32 [H][W]
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipGraphNode_t prep = nullptr, table = nullptr, render = nullptr;
@@ -80,8 +102,10 @@ struct rt_frame_s {
   rt_scene_s* sc = nullptr;
   int W = 0, H = 0;
   bool soft = false, stream_out = false, prefilter = true;
+  int format = RT_FRAME_RGB32F;
   float* rgb = nullptr;     // device image (caller's)
   float* d_pos = nullptr;   // device [N][3]
+  uint32_t* d_px = nullptr; // device packed pixels (RT_FRAME_ARGB8)
   bool built_sky = false;   // the render nodes use the skybox instantiation
   Slot slot[2];
   int64_t submitted = 0;    // frames launched
@@ -202,7 +226,7 @@ rt_status build_graphs(rt_frame_s* f) {
   NodeArgs a;
   fill_args(f, cam, 0, f->soft ? 2 : 1, 1.0f, false, a);
   const size_t pos_bytes = (size_t)f->sc->n_spheres * 3 * sizeof(float);
-  const size_t img_bytes = (size_t)f->W * f->H * 3 * sizeof(float);
+  int64_t n_px = (int64_t)f->W * f->H;
   for (Slot& s : f->slot) {
     FR_TRY(hipGraphCreate(&s.graph, 0), "frame graph");
     hipGraphNode_t last = nullptr;
@@ -221,10 +245,25 @@ rt_status build_graphs(rt_frame_s* f) {
     }
     FR_TRY(hipGraphAddKernelNode(&s.render, s.graph, &last, 1, &a.render_p), "frame render node");
     last = s.render;
-    if (f->stream_out) {
+    if (f->format == RT_FRAME_ARGB8) {
+      const float* src = f->rgb;
+      uint32_t* dst = f->d_px;
+      void* args[3] = {&src, &dst, &n_px};
+      hipKernelNodeParams p{};
+      p.func = (void*)pack_argb_kernel;
+      p.gridDim = dim3((unsigned)((n_px + 255) / 256));
+      p.blockDim = dim3(256);
+      p.kernelParams = args;
+      hipGraphNode_t pack;
+      FR_TRY(hipGraphAddKernelNode(&pack, s.graph, &last, 1, &p), "frame pack node");
       hipGraphNode_t out;
-      FR_TRY(hipGraphAddMemcpyNode1D(&out, s.graph, &last, 1, s.h_rgb, f->rgb, img_bytes,
-                                     hipMemcpyDeviceToHost),
+      FR_TRY(hipGraphAddMemcpyNode1D(&out, s.graph, &pack, 1, s.h_img, f->d_px,
+                                     (size_t)n_px * sizeof(uint32_t), hipMemcpyDeviceToHost),
+             "frame pixels node");
+    } else if (f->stream_out) {
+      hipGraphNode_t out;
+      FR_TRY(hipGraphAddMemcpyNode1D(&out, s.graph, &last, 1, s.h_img, f->rgb,
+                                     (size_t)n_px * 3 * sizeof(float), hipMemcpyDeviceToHost),
              "frame image node");
     }
     FR_TRY(hipGraphInstantiate(&s.exec, s.graph, nullptr, nullptr, 0), "frame graph instantiate");
@@ -241,8 +280,9 @@ void free_frame(rt_frame_s* f) {
   for (Slot& s : f->slot) {
     if (s.done) (void)hipEventDestroy(s.done);
     if (s.h_pos) (void)hipHostFree(s.h_pos);
-    if (s.h_rgb) (void)hipHostFree(s.h_rgb);
+    if (s.h_img) (void)hipHostFree(s.h_img);
   }
+  if (f->d_px) (void)hipFree(f->d_px);
   if (f->d_pos) (void)hipFree(f->d_pos);
   delete f;
 }
@@ -259,6 +299,11 @@ rt_status rt_frame_create(rt_scene scene, const rt_frame_desc* d, rt_frame* out)
   if (d->W <= 0 || d->H <= 0 || d->W > RT_MAX_DIM || d->H > RT_MAX_DIM)
     return fail(RT_ERR_INVALID_ARG, "image %dx%d outside [1, %d]", d->W, d->H, RT_MAX_DIM);
   if (d->soft != 0 && d->soft != 1) return fail(RT_ERR_INVALID_ARG, "soft=%d is not 0 or 1", d->soft);
+  if (d->format != RT_FRAME_RGB32F && d->format != RT_FRAME_ARGB8)
+    return fail(RT_ERR_INVALID_ARG, "format=%d is not RT_FRAME_RGB32F or RT_FRAME_ARGB8",
+                d->format);
+  if (d->format == RT_FRAME_ARGB8 && !d->stream_out)
+    return fail(RT_ERR_INVALID_ARG, "RT_FRAME_ARGB8 pixels are for streaming out: set stream_out");
   if (d->flags & ~(uint32_t)RT_RENDER_NO_PREFILTER)
     return fail(RT_ERR_INVALID_ARG, "unknown render flags 0x%x", d->flags);
   if (!d->rgb_out) return fail(RT_ERR_INVALID_ARG, "rgb_out is NULL");
@@ -269,19 +314,24 @@ rt_status rt_frame_create(rt_scene scene, const rt_frame_desc* d, rt_frame* out)
   f->H = d->H;
   f->soft = d->soft != 0;
   f->stream_out = d->stream_out != 0;
+  f->format = d->format;
   f->prefilter = !(d->flags & RT_RENDER_NO_PREFILTER);
   f->rgb = d->rgb_out;
   const size_t pos_bytes = (size_t)scene->n_spheres * 3 * sizeof(float);
-  const size_t img_bytes = (size_t)f->W * f->H * 3 * sizeof(float);
+  const size_t n_px = (size_t)f->W * f->H;
+  const size_t img_bytes =
+      n_px * (f->format == RT_FRAME_ARGB8 ? sizeof(uint32_t) : 3 * sizeof(float));
   hipError_t e = hipSuccess;
   if (pos_bytes) e = hipMalloc(&f->d_pos, pos_bytes);
+  if (e == hipSuccess && f->format == RT_FRAME_ARGB8)
+    e = hipMalloc(&f->d_px, n_px * sizeof(uint32_t));
   for (Slot& s : f->slot) {
     if (e == hipSuccess && pos_bytes) {
       e = hipHostMalloc(&s.h_pos, pos_bytes, hipHostMallocDefault);
       if (e == hipSuccess) memset(s.h_pos, 0, pos_bytes);
     }
     if (e == hipSuccess && f->stream_out)
-      e = hipHostMalloc(&s.h_rgb, img_bytes, hipHostMallocDefault);
+      e = hipHostMalloc(&s.h_img, img_bytes, hipHostMallocDefault);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
   }
   if (e != hipSuccess) {
@@ -344,14 +394,14 @@ rt_status rt_frame_submit(rt_frame f, const rt_frame_input* in, void* stream) {
   return RT_OK;
 }
 
-rt_status rt_frame_result(rt_frame f, const float** host_rgb) {
+rt_status rt_frame_result(rt_frame f, const void** host_image) {
   if (!f) return fail(RT_ERR_INVALID_ARG, "frame is NULL");
-  if (host_rgb) *host_rgb = nullptr;
+  if (host_image) *host_image = nullptr;
   if (f->returned == f->submitted) return fail(RT_ERR_INVALID_ARG, "no frame is waiting");
   Slot& s = f->slot[f->returned & 1];
   if (s.pending) FR_TRY(hipEventSynchronize(s.done), "frame wait");
   s.pending = false;
-  if (host_rgb) *host_rgb = s.h_rgb;
+  if (host_image) *host_image = s.h_img;
   ++f->returned;
   return RT_OK;
 }

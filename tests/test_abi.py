@@ -165,10 +165,10 @@ def test_set_sky_rejects_bad_arguments_before_any_device_call(rt):
 
 
 def test_frame_rejects_bad_arguments_before_any_device_call(rt):
-    good = dict(W=8, H=8, soft=0, stream_out=0, flags=0, rgb_out=0x1000)
+    good = dict(W=8, H=8, soft=0, stream_out=0, format=0, flags=0, rgb_out=0x1000)
     f = C.c_void_p()
     for field, val in (("W", 0), ("H", -1), ("W", rt.RT_MAX_DIM + 1), ("soft", 2), ("flags", 4),
-                       ("rgb_out", None)):
+                       ("rgb_out", None), ("format", 2), ("format", rt.RT_FRAME_ARGB8)):
         d = rt.rt_frame_desc(**{**good, field: val})
         assert rt._lib.rt_frame_create(FAKE_SCENE, C.byref(d), C.byref(f)) == 1, field
         assert not f.value

@@ -115,6 +115,64 @@ def test_pipelined_frames_keep_their_images(rt):
             rt.rt_frame_destroy(f)
 
 
+def argb8(img):
+    """The packed pixel format, written from its definition: each channel
+    floor(clamp(c, 0, 1) * 255 + 0.5) in FP32, alpha 255 on top."""
+    x = np.clip(np.asarray(img, np.float32), np.float32(0), np.float32(1))
+    q = np.floor(x * np.float32(255) + np.float32(0.5)).astype(np.uint32)
+    return (np.uint32(0xFF000000) | (q[..., 0] << 16) | (q[..., 1] << 8) | q[..., 2])
+
+
+@pytest.mark.parametrize("soft,pipelined", [(False, True), (True, True), (False, False)])
+def test_packed_pixels_stream_out(rt, soft, pipelined):
+    """Packed 32-bit pixels streamed out, with frame k+1 submitted before
+    frame k is taken (pipelined) or each frame taken at once: every frame's
+    pixels equal the packing of the eager float image, and the device float
+    image is the eager image."""
+    s = scenegen.paper_scene()
+    W, H = 150, 83
+    motion = scenegen.verlet_motion(s, 7, seed=5)
+    n, D = scenegen.PAPER_SETTINGS["soft200_3bounces" if soft else "hard_1bounce"]
+    n = n if soft else 1
+    R = scenegen.PAPER_LIGHT_RADIUS if soft else 0.0
+    out = torch.empty((H, W, 3), device="cuda")
+    with rt.SceneHandle(s) as hf, rt.SceneHandle(s) as he:
+        sky = scenegen.sky_map(w=96, h=48)
+        rt.rt_scene_set_sky(hf.handle, sky)
+        rt.rt_scene_set_sky(he.handle, sky)
+        want = [eager(rt, he, moved(s, motion[k]), orbit(k), W, H, D, soft, n, R)
+                for k in range(7)]
+        assert any(((w.numpy() > 1) | (w.numpy() < 0)).any() for w in want)  # clamping is used
+        f = rt.rt_frame_create(hf.handle, W, H, out, soft=soft, stream_out=True,
+                               fmt=rt.RT_FRAME_ARGB8)
+        try:
+            if pipelined:
+                rt.rt_frame_submit(f, orbit(0), D, n, R, motion[0])
+                for k in range(1, 7):
+                    rt.rt_frame_submit(f, orbit(k), D, n, R, motion[k])
+                    px = rt.rt_frame_result(f, W, H, rt.RT_FRAME_ARGB8)    # frame k - 1
+                    assert px.dtype == np.uint32 and px.shape == (H, W)
+                    assert np.array_equal(px, argb8(want[k - 1].numpy())), k
+            else:
+                for k in range(6):
+                    rt.rt_frame_submit(f, orbit(k), D, n, R, motion[k])
+                    px = rt.rt_frame_result(f, W, H, rt.RT_FRAME_ARGB8)    # frame k
+                    assert np.array_equal(px, argb8(want[k].numpy())), k
+                rt.rt_frame_submit(f, orbit(6), D, n, R, motion[6])
+            px = rt.rt_frame_result(f, W, H, rt.RT_FRAME_ARGB8)
+            assert np.array_equal(px, argb8(want[6].numpy()))
+            assert torch.equal(out.cpu(), want[6])
+            # a skybox removed between frames rebuilds the graphs
+            rt.rt_scene_set_sky(hf.handle, None)
+            rt.rt_scene_set_sky(he.handle, None)
+            rt.rt_frame_submit(f, orbit(6), D, n, R, None)
+            px = rt.rt_frame_result(f, W, H, rt.RT_FRAME_ARGB8)
+            ref = eager(rt, he, moved(s, motion[6]), orbit(6), W, H, D, soft, n, R)
+            assert np.array_equal(px, argb8(ref.numpy()))
+        finally:
+            rt.rt_frame_destroy(f)
+
+
 def test_frame_matches_oracle(rt, oracle_mod):
     s = scenegen.paper_scene()
     W, H = 192, 108
