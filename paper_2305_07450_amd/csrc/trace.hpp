@@ -940,18 +940,47 @@ __device__ __forceinline__ void perp_basis(float wx, float wy, float wz, float& 
   bz = -wy;
 }
 
-// Exact test of one sphere against the sample rays of the lanes not yet
-// blocked: a root in (t_min, dist) of a sphere other than the surface.
-__device__ __forceinline__ void soft_blocker(float4 g, int i, const Ray& sr, float dist, float tmin,
-                                             int self, bool& blk) {
-  float b;
-  const float ff = sphere_ff(g, sr, b);
-  const bool in = !blk & (ff <= g.w) & (i != self);
-  if (wave_any(in)) {
-    const float sq = fsqrt(in ? g.w - ff : 0.0f);
-    const float t0 = -b - sq, t1 = -b + sq;
-    blk = blk || (in && ((t0 > tmin && t0 < dist) || (t1 > tmin && t1 < dist)));
+// Sample rays traced together by each lane: independent chains that the
+// SIMD interleaves, one ballot per sphere for the whole group, and one o - c
+// per sphere, since every sample ray of a lane starts at its hit point.
+constexpr int kSoftGroup = 8;
+
+// Exact test of one sphere against a group of sample rays of the lanes, for
+// the rays not yet blocked: a root in (t_min, dist) of a sphere other than
+// the surface.  The arithmetic per ray is sphere_ff's.
+__device__ __forceinline__ void soft_blockers(float4 g, int i, const Surface& f, const float* dx,
+                                              const float* dy, const float* dz,
+                                              const float* dist, float tmin, int self,
+                                              bool* blk) {
+  const float ocx = f.px - g.x, ocy = f.py - g.y, ocz = f.pz - g.z;
+  float b[kSoftGroup], ff[kSoftGroup];
+  bool in[kSoftGroup];
+  bool any = false;
+#pragma unroll
+  for (int k = 0; k < kSoftGroup; ++k) {
+    b[k] = dot3(ocx, ocy, ocz, dx[k], dy[k], dz[k]);
+    const float fx = fmaf(-b[k], dx[k], ocx);
+    const float fy = fmaf(-b[k], dy[k], ocy);
+    const float fz = fmaf(-b[k], dz[k], ocz);
+    ff[k] = dot3(fx, fy, fz, fx, fy, fz);
+    in[k] = !blk[k] & (ff[k] <= g.w) & (i != self);
+    any |= in[k];
   }
+  if (wave_any(any)) {
+#pragma unroll
+    for (int k = 0; k < kSoftGroup; ++k) {
+      const float sq = fsqrt(in[k] ? g.w - ff[k] : 0.0f);
+      const float t0 = -b[k] - sq, t1 = -b[k] + sq;
+      blk[k] = blk[k] | (in[k] & (((t0 > tmin) & (t0 < dist[k])) | ((t1 > tmin) & (t1 < dist[k]))));
+    }
+  }
+}
+
+__device__ __forceinline__ bool any_open(const bool* blk) {
+  bool o = false;
+#pragma unroll
+  for (int k = 0; k < kSoftGroup; ++k) o |= !blk[k];
+  return o;
 }
 
 // Share of light l's sample points whose shadow rays from the hit point p
@@ -1008,47 +1037,63 @@ __device__ __forceinline__ float soft_visibility(const SceneDev& s, float4 q, co
   }
   int visible = 0;
   // the table is read 8 samples (64 bytes) per scalar load; it holds a
-  // multiple of 8 entries, so the last block stays inside it
+  // multiple of 8 entries, so the last block stays inside it (entries past n
+  // are read but count as blocked)
+  static_assert(8 % kSoftGroup == 0, "sample groups split a table block");
   for (int i0 = 0; i0 < sh.n; i0 += 8) {
-  const rt_v16 tb = ((const RT_CONSTANT rt_v16*)sh.table)[i0 >> 3];
+    const rt_v16 tb = ((const RT_CONSTANT rt_v16*)sh.table)[i0 >> 3];
 #pragma unroll
-  for (int kk = 0; kk < 8; ++kk) {
-    const int i = i0 + kk;
-    if (i >= sh.n) break;
-    const float u = sh.radius * tb[2 * kk], v = sh.radius * tb[2 * kk + 1];
-    float dx = fmaf(u, ax, fmaf(v, bx, q.x)) - f.px;
-    float dy = fmaf(u, ay, fmaf(v, by, q.y)) - f.py;
-    float dz = fmaf(u, az, fmaf(v, bz, q.z)) - f.pz;
-    const float d2 = dot3(dx, dy, dz, dx, dy, dz);
-    const float inv = frsq(d2);
-    const float di = d2 * inv;
-    dx *= inv; dy *= inv; dz *= inv;
-    bool blk = !act || !(dot3(f.nx, f.ny, f.nz, dx, dy, dz) > 0.0f);
-    if (wave_any(!blk)) {
-      Ray sr;
-      sr.ox = f.px; sr.oy = f.py; sr.oz = f.pz;
-      sr.dx = dx; sr.dy = dy; sr.dz = dz;
-      if (culled) {
+    for (int k0 = 0; k0 < 8; k0 += kSoftGroup) {
+      if (i0 + k0 >= sh.n) break;
+      float dx[kSoftGroup], dy[kSoftGroup], dz[kSoftGroup], di[kSoftGroup];
+      bool blk[kSoftGroup];
 #pragma unroll
-        for (int c = 0; c < kSoftChunks; ++c) {
-          uint64_t m = cand[c];
-          while (m) {
-            const int k = (int)__builtin_ctzll(m);
-            m &= m - 1;
-            soft_blocker(ld4(s.geom, 64 * c + k), 64 * c + k, sr, di, tmin, self, blk);
-            if (!wave_any(!blk)) m = 0;
+      for (int k = 0; k < kSoftGroup; ++k) {
+        const int kk = k0 + k;
+        const float u = sh.radius * tb[2 * kk], v = sh.radius * tb[2 * kk + 1];
+        float x = fmaf(u, ax, fmaf(v, bx, q.x)) - f.px;
+        float y = fmaf(u, ay, fmaf(v, by, q.y)) - f.py;
+        float z = fmaf(u, az, fmaf(v, bz, q.z)) - f.pz;
+        const float d2 = dot3(x, y, z, x, y, z);
+        const float inv = frsq(d2);
+        di[k] = d2 * inv;
+        dx[k] = x * inv; dy[k] = y * inv; dz[k] = z * inv;
+        blk[k] = (i0 + kk >= sh.n) | !act | !(dot3(f.nx, f.ny, f.nz, dx[k], dy[k], dz[k]) > 0.0f);
+      }
+      if (wave_any(any_open(blk))) {
+        if (culled) {
+#pragma unroll
+          for (int c = 0; c < kSoftChunks; ++c) {
+            uint64_t m = cand[c];
+            while (m) {
+              const int k = (int)__builtin_ctzll(m);
+              m &= m - 1;
+              soft_blockers(ld4(s.geom, 64 * c + k), 64 * c + k, f, dx, dy, dz, di, tmin, self,
+                            blk);
+              if (!wave_any(any_open(blk))) m = 0;
+            }
+          }
+        } else {
+          scan_spheres(
+              s.geom, s.n4,
+              [&](int j, float4 g) { soft_blockers(g, j, f, dx, dy, dz, di, tmin, self, blk); },
+              [&] { return !wave_any(any_open(blk)); });
+        }
+        for (int j = 0; j < s.n_planes; ++j) {
+          const float4 pg = ld4(s.pgeom, j);
+          const bool other = s.n_spheres + j != self;
+#pragma unroll
+          for (int k = 0; k < kSoftGroup; ++k) {
+            Ray sr;
+            sr.ox = f.px; sr.oy = f.py; sr.oz = f.pz;
+            sr.dx = dx[k]; sr.dy = dy[k]; sr.dz = dz[k];
+            blk[k] = blk[k] | (other & (plane_root(pg, sr, tmin) < di[k]));
           }
         }
-      } else {
-        scan_spheres(
-            s.geom, s.n4, [&](int j, float4 g) { soft_blocker(g, j, sr, di, tmin, self, blk); },
-            [&] { return !wave_any(!blk); });
       }
-      for (int j = 0; j < s.n_planes; ++j)
-        blk = blk || (s.n_spheres + j != self && plane_root(ld4(s.pgeom, j), sr, tmin) < di);
+#pragma unroll
+      for (int k = 0; k < kSoftGroup; ++k) visible += blk[k] ? 0 : 1;
     }
-    visible += blk ? 0 : 1;
-  }
   }
   return act ? (float)visible / (float)sh.n : 0.0f;
 }
