@@ -225,7 +225,7 @@ def bench_interactive(rt, scenegen, stream, frames=60):
     the image out to pinned host memory (rt_frame_*); frame k+1 is submitted
     before frame k is taken.  Host wall clock per frame, both settings, 720p,
     1080p and 4K, with the paper's 32-bit pixels (packed on the device) and
-    with the float image."""
+    with the float image; the median of three runs of `frames` frames."""
     import time
     s = scenegen.paper_scene()
     warm = 4
@@ -255,11 +255,15 @@ def bench_interactive(rt, scenegen, stream, frames=60):
                     rt.rt_frame_result(f)
 
                 run(0, warm)
-                t0 = time.perf_counter()
-                run(warm, frames)
-                ms = (time.perf_counter() - t0) * 1e3 / frames
+                reps = []
+                for _ in range(3):   # host-side copies vary between runs: median of three
+                    t0 = time.perf_counter()
+                    run(warm, frames)
+                    reps.append((time.perf_counter() - t0) * 1e3 / frames)
                 rt.rt_frame_destroy(f)
+                ms = sorted(reps)[1]
                 res[f"{fmt_name}_{W}x{H}"] = {"ms": round(ms, 4), "fps": round(1e3 / ms, 1),
+                                             "ms_runs": [round(r, 4) for r in reps],
                                              "stream_out_MB": round(W * H * bpp / 1e6, 2)}
         out[name] = {"samples": n, "depth": D, **res}
     h.close()
