@@ -261,3 +261,27 @@ def test_frame_rejects_bad_inputs(rt):
         finally:
             rt.rt_frame_destroy(hard)
             rt.rt_frame_destroy(soft)
+
+
+def test_frames_of_small_and_empty_scenes(rt):
+    """A 1x1 image, a scene without spheres (no positions to stream) and a
+    scene without lights run through the frame path as through the eager
+    one."""
+    cases = [("one pixel", scenegen.paper_scene(), 1, 1),
+             ("no spheres", scenegen.tiny_scene(3, n_spheres=0, n_lights=2), 33, 17),
+             ("no lights", scenegen.tiny_scene(4, n_spheres=7, n_lights=0), 29, 31)]
+    for name, s, W, H in cases:
+        log("case frame", name)
+        out = torch.empty((H, W, 3), device="cuda")
+        pos = scenegen.verlet_motion(s, 3, seed=2)
+        with rt.SceneHandle(s) as hf, rt.SceneHandle(s) as he:
+            f = rt.rt_frame_create(hf.handle, W, H, out, stream_out=True, fmt=rt.RT_FRAME_ARGB8)
+            try:
+                for k in range(3):
+                    rt.rt_frame_submit(f, orbit(k), 2, 1, 0.0, pos[k] if pos.shape[1] else None)
+                    px = rt.rt_frame_result(f, W, H, rt.RT_FRAME_ARGB8)
+                    want = eager(rt, he, moved(s, pos[k]), orbit(k), W, H, 2, False, 1, 0.0)
+                    assert torch.equal(out.cpu(), want), (name, k)
+                    assert np.array_equal(px, argb8(want.numpy())), (name, k)
+            finally:
+                rt.rt_frame_destroy(f)

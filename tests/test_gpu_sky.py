@@ -222,3 +222,37 @@ def test_backward_refuses_a_sky(rt):
         rt.rt_render_backward(h.handle, cam, W, H, D, g, grads)
         torch.cuda.synchronize()
         assert torch.isfinite(grads["albedo"]).all()
+
+
+@pytest.mark.parametrize("mw,mh", [(1, 1), (1, 7), (9, 1), (2, 2)])
+def test_degenerate_maps(rt, oracle_mod, mw, mh):
+    """Maps one texel wide or high: the wrap and the clamp fold onto the same
+    texels."""
+    s = scenegen.tiny_scene(950, n_spheres=6, n_lights=1)
+    sky = scenegen.sky_map(seed=mw * 10 + mh, w=mw, h=mh)
+    cam = Camera(yaw_deg=160.0, pitch_deg=20.0, fov_deg=110.0)
+    W, H, D = 40, 30, 2
+    log("case degenerate map", mw, mh)
+    g = gpu_render(rt, s, cam, W, H, D, sky=sky)
+    compare(oracle_mod, s, cam, W, H, D, g, label=f"map{mw}x{mh}", sky=sky)
+
+
+def test_coordinate_map_across_seam_and_pole(rt, oracle_mod):
+    """An empty scene under a coordinate map (texel (i, j) holds
+    ((i + 1/2)/w, (j + 1/2)/h, 0)), seen looking back across the seam and up
+    past the pole: the image is the UV mapping itself."""
+    z4 = np.zeros((0, 4), np.float32)
+    z1 = np.zeros(0, np.float32)
+    s = scenegen.Scene(sphere_geom=z4, sphere_mat=z4, sphere_shine=z1, plane_geom=z4,
+                       plane_mat=z4, plane_shine=z1, light=z4)
+    w, h = 90, 45
+    m = np.zeros((h, w, 3), np.float32)
+    m[..., 0] = ((np.arange(w) + 0.5) / w)[None, :]
+    m[..., 1] = ((np.arange(h) + 0.5) / h)[:, None]
+    W, H = 160, 120
+    for cam in (Camera(yaw_deg=180.0, fov_deg=100.0), Camera(pitch_deg=70.0, fov_deg=100.0)):
+        log("case coordinate map", cam.yaw_deg, cam.pitch_deg)
+        g = gpu_render(rt, s, cam, W, H, 0, sky=m)
+        stats, base = compare(oracle_mod, s, cam, W, H, 0, g, label="coordmap", sky=m)
+        assert (base.prim_id == -1).all()
+        assert stats["ill_conditioned"] < 0.05, stats

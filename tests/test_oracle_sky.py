@@ -68,3 +68,27 @@ def test_mirror_floor_reflects_the_sky(oracle_mod):
     assert r.prim_id[0] == 0                   # the plane
     ka = float(s.ambient)
     np.testing.assert_allclose(r.rgb[0], [ka * 0.5, ka / 3.0, 0.0], rtol=0, atol=1e-12)
+
+
+def test_seam_wraps_around(oracle_mod):
+    """Looking along +z puts u at 1, on the seam: x = w - 1/2 falls halfway
+    between the last column and, wrapped around, the first, so the
+    coordinate map gives (w - 1/2 + 1/2) / (2 w) = 1/2 in red.  Clamping
+    instead of wrapping would give (w - 1/2) / w."""
+    W, H = 64, 36
+    m = coord_map(w=360, h=180)
+    r = oracle_mod.render(empty_scene(), Camera(yaw_deg=180.0), W, H, 0,
+                          pixels=np.array([(H // 2) * W + W // 2]), sky=m)
+    np.testing.assert_allclose(r.rgb[0], [0.5, 0.5, 0.0], rtol=0, atol=1e-9)
+
+
+def test_pole_clamps_to_the_top_row(oracle_mod):
+    """Near straight up, y = v h - 1/2 < 0 lies above the first row's centre:
+    both bilinear rows clamp to row 0, so green is that row's value 1/(2 h)
+    exactly, where extrapolating would give less."""
+    W, H = 64, 36
+    h = 180
+    r = oracle_mod.render(empty_scene(), Camera(pitch_deg=89.9), W, H, 0,
+                          pixels=np.array([(H // 2) * W + W // 2]), sky=coord_map(w=360, h=h))
+    np.testing.assert_allclose(r.rgb[0, 1], 0.5 / h, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(r.rgb[0, 0], 0.5, rtol=0, atol=1e-9)
