@@ -144,8 +144,7 @@ rt_status rt_scene_update(rt_scene scene, const rt_scene_desc* desc, void* strea
  * (row 0 straight up, u = 1/2 along -z); the colour is bilinear between
  * texel centres (x = u w - 1/2, y = v h - 1/2), wrapping around in x and
  * clamped to the edge rows in y.  Every render entry point then uses it on
- * a miss; rt_render_backward refuses scenes with a skybox
- * (RT_ERR_UNSUPPORTED).
+ * a miss, and rt_render_backward differentiates through it.
  *   rgb   host or device pointer per `mem`; copied, the caller keeps it;
  *   w, h  1 .. RT_MAX_SKY_DIM; rgb == NULL with w == h == 0 removes the
  *         skybox.
@@ -224,8 +223,10 @@ rt_status rt_render_counts(rt_scene scene, const rt_camera* cam, int32_t W, int3
  * shadow occluders carry no gradient.  With rec == NULL the decisions are
  * recomputed by re-tracing; otherwise they are read from records written by
  * rt_render for the same scene, camera, size and depth.  The sum over pixels
- * is deterministic (fixed order, no floating-point atomics).  A scene with
- * a skybox is refused (RT_ERR_UNSUPPORTED).  No allocation; capture-safe. */
+ * is deterministic (fixed order, no floating-point atomics).  With a skybox,
+ * a path that ends in a miss also feeds its last mirror direction through
+ * the UV mapping and the bilinear weights (texels are constants).  No
+ * allocation; capture-safe. */
 rt_status rt_render_backward(rt_scene scene, const rt_camera* cam, int32_t W, int32_t H,
                              int32_t depth, const float* grad_rgb, const rt_records* rec,
                              const rt_grads* grads, void* stream);

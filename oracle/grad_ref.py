@@ -18,11 +18,15 @@ rounding, and central finite differences of the C oracle pin the gradient.
 Differentiated parameters: sphere albedo [N,3], sphere reflection ratio [N],
 sphere centre [N,3], light position [L,3], light intensity [L].  Radii,
 exponents, planes, ambient and k_s are constants; shadow occluders carry no
-gradient.
+gradient.  With a skybox (Section 3.8) a path that ends in a miss adds T times
+the map's bilinear colour in the ray's direction, written out as the C oracle
+computes it; its texels are constants, and autograd differentiates through
+the UV mapping and the bilinear weights (the texel indices are decisions).
 """
 
 from __future__ import annotations
 
+import math
 from typing import Dict
 
 import numpy as np
@@ -44,9 +48,29 @@ def _dot(a, b):
     return (a * b).sum(-1)
 
 
+def _sky(sky: torch.Tensor, d: torch.Tensor) -> torch.Tensor:
+    """Bilinear skybox colour [n,3] in directions d [n,3]: u = 1/2 +
+    atan2(d_x, -d_z)/(2 pi), v = 1/2 - asin(d_y)/pi, texel centres at
+    x = u w - 1/2, y = v h - 1/2, wrapping in x and clamping in y."""
+    h, w = sky.shape[0], sky.shape[1]
+    u = 0.5 + torch.atan2(d[:, 0], -d[:, 2]) / (2.0 * math.pi)
+    v = 0.5 - torch.asin(torch.clamp(d[:, 1], -1.0, 1.0)) / math.pi
+    x = u * w - 0.5
+    y = v * h - 0.5
+    fx, fy = torch.floor(x.detach()), torch.floor(y.detach())
+    ax, ay = (x - fx)[:, None], (y - fy)[:, None]
+    x0, y0 = fx.long(), fy.long()
+    xs = [torch.remainder(x0 + k, w) for k in (0, 1)]
+    ys = [torch.clamp(y0 + k, 0, h - 1) for k in (0, 1)]
+    t = lambda yi, xi: sky[yi, xi]
+    return ((1.0 - ay) * ((1.0 - ax) * t(ys[0], xs[0]) + ax * t(ys[0], xs[1]))
+            + ay * ((1.0 - ax) * t(ys[1], xs[0]) + ax * t(ys[1], xs[1])))
+
+
 def reshade(params: Dict[str, torch.Tensor], scene: Scene, o0: np.ndarray, d0: np.ndarray,
-            seg_id: np.ndarray, lit: np.ndarray, depth: int) -> torch.Tensor:
-    """Colour [n,3] of n paths with fixed records (seg_id, lit: [n, depth+1])."""
+            seg_id: np.ndarray, lit: np.ndarray, depth: int, sky=None) -> torch.Tensor:
+    """Colour [n,3] of n paths with fixed records (seg_id, lit: [n, depth+1]);
+    `sky` is the skybox [h, w, 3] or None for the plain background."""
     dt = torch.float64
     N, P, L = scene.n_spheres, scene.n_planes, scene.n_lights
     radius = torch.tensor(scene.sphere_geom[:, 3], dtype=dt)
@@ -55,6 +79,7 @@ def reshade(params: Dict[str, torch.Tensor], scene: Scene, o0: np.ndarray, d0: n
     palb = torch.tensor(scene.plane_mat[:, :3], dtype=dt)
     pkr = torch.tensor(scene.plane_mat[:, 3], dtype=dt)
     bg = torch.tensor(scene.background, dtype=dt)
+    sky_t = torch.tensor(np.asarray(sky, dtype=np.float64)) if sky is not None else None
     ka, ks, tmin = float(scene.ambient), float(scene.spec_strength), float(scene.t_min)
     albedo = torch.cat([params["albedo"], palb], 0)         # [N+P, 3]
     kr_all = torch.cat([params["refl"], pkr], 0)            # [N+P]
@@ -69,7 +94,10 @@ def reshade(params: Dict[str, torch.Tensor], scene: Scene, o0: np.ndarray, d0: n
     for k in range(depth + 1):
         idk = seg[:, k]
         miss = alive & (idk == -1)
-        C = C + torch.where(miss[:, None], T[:, None] * bg, torch.zeros_like(C))
+        if sky_t is not None and bool(miss.any()):
+            C = C + torch.where(miss[:, None], T[:, None] * _sky(sky_t, d), torch.zeros_like(C))
+        else:
+            C = C + torch.where(miss[:, None], T[:, None] * bg, torch.zeros_like(C))
         hit = alive & (idk >= 0)
         if not bool(hit.any()):
             break
@@ -147,11 +175,11 @@ def reshade(params: Dict[str, torch.Tensor], scene: Scene, o0: np.ndarray, d0: n
 
 
 def masked_loss_grad(scene: Scene, o0, d0, seg_id, lit, depth, target_rgb: np.ndarray,
-                     mask: np.ndarray):
+                     mask: np.ndarray, sky=None):
     """Loss = sum over masked pixels of |C - target|^2; returns (loss, grads,
     rgb) with grads a dict of float64 numpy arrays keyed by PARAM_NAMES."""
     prm = params_of(scene)
-    C = reshade(prm, scene, o0, d0, seg_id, lit, depth)
+    C = reshade(prm, scene, o0, d0, seg_id, lit, depth, sky)
     diff = (C - torch.tensor(target_rgb, dtype=torch.float64)) * torch.tensor(
         mask.astype(np.float64))[:, None]
     loss = (diff * diff).sum()
@@ -159,10 +187,10 @@ def masked_loss_grad(scene: Scene, o0, d0, seg_id, lit, depth, target_rgb: np.nd
     return float(loss.detach()), _grads(prm), C.detach().numpy()
 
 
-def vjp(scene: Scene, o0, d0, seg_id, lit, depth, grad_rgb: np.ndarray):
+def vjp(scene: Scene, o0, d0, seg_id, lit, depth, grad_rgb: np.ndarray, sky=None):
     """Gradient of sum(grad_rgb * C) with respect to every parameter group."""
     prm = params_of(scene)
-    C = reshade(prm, scene, o0, d0, seg_id, lit, depth)
+    C = reshade(prm, scene, o0, d0, seg_id, lit, depth, sky)
     (C * torch.tensor(grad_rgb, dtype=torch.float64)).sum().backward()
     return _grads(prm)
 

@@ -5,14 +5,16 @@
 // same closest-hit and shadow code as the forward pass), giving bit-identical
 // hit points.  The reverse sweep runs over the segments from the last to the
 // first:
-//   C = sum_k T_k (A_k w_k a_k + S_k) [+ T_K bg at a miss],
+//   C = sum_k T_k (A_k w_k a_k + S_k) [+ T_K bg, or T_K sky(d_K), at a miss],
 //   T_{k+1} = T_k A_k kr_k,  w_k = 1 - kr_k (k < depth), 1 (k = depth),
 //   U_k = dL/dT_k = A_k (w_k g.a_k + kr_k U_{k+1}) + S_k (g_r + g_g + g_b),
 // then through the Blinn/Phong light terms (Section 3.5) into the normal, the
 // hit point and the light, and through p = o + t d, n = (p - c)/r, the root
 // t(o, d, c) (dt/dc = n/(n.d)) and the mirror ray (Section 3.7) into the
 // previous segment's ray.  Shadow occluders, radii, exponents and planes are
-// constants.
+// constants.  A miss under a skybox (Section 3.8) also feeds the mirror
+// direction d_K through the UV mapping and the bilinear weights (the texels
+// and their indices are constants).
 //
 // Summation is deterministic: each wave reduces the contributions of one
 // sphere id with a fixed xor butterfly and adds them into its own LDS
@@ -71,6 +73,57 @@ __device__ __forceinline__ void light_terms_fixed(const SceneDev& s, const Surfa
     float x = spec_base(s.spec_model, f.nx, f.ny, f.nz, lx, ly, lz, -r.dx, -r.dy, -r.dz, nl);
     S = fmaf(q.w * s.spec_strength, spec_pow(x, f.shine), S);
   }
+}
+
+// Gradient with respect to the unit direction d of g . sky(d), the skybox
+// colour that sky_colour() looks up: u = 1/2 + atan2(d_x, -d_z) / (2 pi),
+// v = 1/2 - asin(d_y) / pi, bilinear weights (x - x0, y - y0) with
+// x = u w - 1/2, y = v h - 1/2.  Within a texel cell the colour is bilinear in
+// (x, y); clamped rows give equal texels and no v term.  The result is
+// projected onto the plane orthogonal to d (the colour depends on the
+// direction only); at the poles, where u is undefined, its u term is dropped.
+__device__ __forceinline__ void sky_grad(const SceneDev& s, float dx, float dy, float dz,
+                                         float gr, float gg, float gb, float& ox, float& oy,
+                                         float& oz) {
+  constexpr float kInvTwoPi = 0.15915494309189535f;
+  constexpr float kInvPi = 0.3183098861837907f;
+  const int w = s.sky_w, h = s.sky_h;
+  const float u = fmaf(atan2f(dx, -dz), kInvTwoPi, 0.5f);
+  const float cdy = fminf(fmaxf(dy, -1.0f), 1.0f);
+  const float v = fmaf(-asinf(cdy), kInvPi, 0.5f);
+  const float x = fmaf(u, (float)w, -0.5f);
+  const float y = fmaf(v, (float)h, -0.5f);
+  const float fx = floorf(x), fy = floorf(y);
+  const float ax = x - fx, ay = y - fy;
+  int x0 = (int)fx, y0 = (int)fy;
+  x0 = x0 < 0 ? x0 + w : x0;
+  int x1 = x0 + 1 >= w ? x0 + 1 - w : x0 + 1;
+  x0 = min(max(x0, 0), w - 1);
+  x1 = min(max(x1, 0), w - 1);
+  const int y1 = min(max(y0 + 1, 0), h - 1);
+  y0 = min(max(y0, 0), h - 1);
+  const float4 t00 = s.sky[y0 * w + x0], t10 = s.sky[y0 * w + x1];
+  const float4 t01 = s.sky[y1 * w + x0], t11 = s.sky[y1 * w + x1];
+  // g . texel
+  const float c00 = gr * t00.x + gg * t00.y + gb * t00.z;
+  const float c10 = gr * t10.x + gg * t10.y + gb * t10.z;
+  const float c01 = gr * t01.x + gg * t01.y + gb * t01.z;
+  const float c11 = gr * t11.x + gg * t11.y + gb * t11.z;
+  const float dax = (1.0f - ay) * (c10 - c00) + ay * (c11 - c01);   // d/d ax
+  const float day = ((1.0f - ax) * c01 + ax * c11) - ((1.0f - ax) * c00 + ax * c10);
+  const float du = dax * (float)w, dv = day * (float)h;
+  const float rxz = dx * dx + dz * dz;
+  float gx = 0.0f, gy = 0.0f, gz = 0.0f;
+  if (rxz > 1e-12f) {
+    gx = du * kInvTwoPi * (-dz / rxz);
+    gz = du * kInvTwoPi * (dx / rxz);
+  }
+  const float cy2 = 1.0f - cdy * cdy;
+  if (cy2 > 1e-12f) gy = -dv * kInvPi / sqrtf(cy2);
+  const float rad = gx * dx + gy * dy + gz * dz;
+  ox = gx - rad * dx;
+  oy = gy - rad * dy;
+  oz = gz - rad * dz;
 }
 
 // Hit distance of a known primitive: the same root the closest-hit search
@@ -176,9 +229,12 @@ __global__ __launch_bounds__(256) void adjoint_kernel(SceneDev s, CameraDev c, i
         }
       }
 
-      // forward replay: ray and throughput of every hit segment
+      // forward replay: ray and throughput of every hit segment, then those of
+      // the segment after the last hit
       Ray rays[kMaxDepth + 1];
       float Ts[kMaxDepth + 1];
+      Ray r_end;
+      float T_end;
       {
         Ray r = primary_ray(c, valid ? x : 0, valid ? y : 0);
         float T = 1.0f;
@@ -194,12 +250,25 @@ __global__ __launch_bounds__(256) void adjoint_kernel(SceneDev s, CameraDev c, i
             reflect_ray(r, f);
           }
         }
+        r_end = r;
+        T_end = T;
       }
 
       // reverse sweep
       const float gsum = gr + gg + gb;
       float U = ends_in_miss ? (gr * s.bg_r + gg * s.bg_g + gb * s.bg_b) : 0.0f;
       V3 obar = {0.f, 0.f, 0.f}, dbar = {0.f, 0.f, 0.f};
+      if (s.sky && ends_in_miss) {
+        // the miss shows the sky in the direction of the segment after the
+        // last hit: U = g . sky(d_K), and d_K gets T_K grad_d (g . sky)
+        float br, bgc, bb;
+        sky_colour(s, r_end.dx, r_end.dy, r_end.dz, br, bgc, bb);
+        U = gr * br + gg * bgc + gb * bb;
+        if (K > 0) {
+          sky_grad(s, r_end.dx, r_end.dy, r_end.dz, gr, gg, gb, dbar.x, dbar.y, dbar.z);
+          dbar.x *= T_end; dbar.y *= T_end; dbar.z *= T_end;
+        }
+      }
       for (int k = depth; k >= 0; --k) {
         // every lane runs the same k so that the wave-wide reductions below line up
         const bool active = valid && k < K;

@@ -422,9 +422,6 @@ rt_status rt_render_backward(rt_scene sc, const rt_camera* cam, int32_t W, int32
   if (!grad_rgb) return fail(RT_ERR_INVALID_ARG, "grad_rgb is NULL");
   if (!grads) return fail(RT_ERR_INVALID_ARG, "grads is NULL");
   if ((st = check_records(rec, W, H, depth)) != RT_OK) return st;
-  if (sc->sky)
-    return fail(RT_ERR_UNSUPPORTED, "rt_render_backward does not differentiate a skybox; remove it "
-                "with rt_scene_set_sky(scene, NULL, 0, 0, ...)");
   if (!adjoint_supported(sc->n_spheres))
     return fail(RT_ERR_UNSUPPORTED, "rt_render_backward supports at most 2335 spheres, scene has %d",
                 sc->n_spheres);

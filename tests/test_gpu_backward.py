@@ -36,8 +36,11 @@ def _alloc(scene):
     return {k: torch.full(s, float("nan"), device="cuda") for k, s in shapes.items()}
 
 
-def run_gpu(rt, scene, cam, W, H, D, target_rgb=None, grad_rgb=None, mode="checkpoint"):
+def run_gpu(rt, scene, cam, W, H, D, target_rgb=None, grad_rgb=None, mode="checkpoint",
+            sky=None):
     with rt.SceneHandle(scene) as h:
+        if sky is not None:
+            rt.rt_scene_set_sky(h.handle, sky)
         rgb, ids, rec = rt.render(h.handle, cam, W, H, D, ids=True, records=True)
         torch.cuda.synchronize()
         out = dict(rgb=rgb.cpu().numpy().reshape(-1, 3).astype(np.float64),
@@ -53,21 +56,22 @@ def run_gpu(rt, scene, cam, W, H, D, target_rgb=None, grad_rgb=None, mode="check
     return out
 
 
-def reference_check(rt, oracle_mod, scene, cam, W, H, D, target, label):
+def reference_check(rt, oracle_mod, scene, cam, W, H, D, target, label, sky=None):
     from oracle import grad_ref
-    fwd = run_gpu(rt, scene, cam, W, H, D)
-    base = oracle_mod.render(scene, cam, W, H, D)
-    ok = oracle_mod.condition(scene, cam, W, H, D, base=base)
+    fwd = run_gpu(rt, scene, cam, W, H, D, sky=sky)
+    base = oracle_mod.render(scene, cam, W, H, D, sky=sky)
+    ok = oracle_mod.condition(scene, cam, W, H, D, base=base, sky=sky)
     same = (fwd["seg"] == base.seg_id).all(1) & (fwd["lit"] == base.lit).all(1)
     mask = same & ok & ~oracle_mod.id_edges(base.prim_id, W, H, 2)
-    tgt = oracle_mod.render(target, cam, W, H, D, records=False, margins=False).rgb
+    tgt = oracle_mod.render(target, cam, W, H, D, records=False, margins=False, sky=sky).rgb
     grad_rgb = 2.0 * (fwd["rgb"] - tgt) * mask[:, None]
     grad_rgb = grad_rgb.astype(np.float32).astype(np.float64)
     res = {}
     for mode in ("checkpoint", "recompute"):
-        res[mode] = run_gpu(rt, scene, cam, W, H, D, grad_rgb=grad_rgb, mode=mode)["grads"]
+        res[mode] = run_gpu(rt, scene, cam, W, H, D, grad_rgb=grad_rgb, mode=mode,
+                            sky=sky)["grads"]
     o0, d0 = oracle_mod.camera_rays(cam, W, H, np.arange(W * H))
-    ref = grad_ref.vjp(scene, o0, d0, base.seg_id, base.lit, D, grad_rgb)
+    ref = grad_ref.vjp(scene, o0, d0, base.seg_id, base.lit, D, grad_rgb, sky)
     errs = {}
     for k in GROUPS:
         g = res["checkpoint"][k]
@@ -88,6 +92,22 @@ def test_small_scene_against_reference(rt, oracle_mod, model, seed):
     s = scenegen.random_scene(rng, 8, 2, spec_model=model)
     target = scenegen.perturb_scene(s, np.random.default_rng(seed + 50))
     reference_check(rt, oracle_mod, s, Camera(), W, H, D, target, f"small seed={seed}")
+
+
+@pytest.mark.parametrize("model,seed", [(SPEC_BLINN, 20), (SPEC_PHONG, 21)])
+def test_small_scene_with_sky_against_reference(rt, oracle_mod, model, seed):
+    """A skybox seen through mirror bounces: the misses feed the sphere
+    centres through the UV mapping and the bilinear weights."""
+    W, H, D = 96, 54, 3
+    rng = np.random.default_rng(seed)
+    s = scenegen.random_scene(rng, 8, 2, spec_model=model)
+    target = scenegen.perturb_scene(s, np.random.default_rng(seed + 50))
+    sky = scenegen.sky_map(seed=seed, w=64, h=32)
+    cam = Camera(pitch_deg=8.0)
+    _, ref, mask, _ = reference_check(rt, oracle_mod, s, cam, W, H, D, target,
+                                      f"sky seed={seed}", sky=sky)
+    base = oracle_mod.render(s, cam, W, H, D)
+    assert ((base.seg_id[:, 0] >= 0) & (base.seg_id == -1).any(1) & mask).sum() > 20
 
 
 def test_workload4_against_reference(rt, oracle_mod):

@@ -207,23 +207,6 @@ def test_batch_with_skies_bit_exact_and_stale_sky_refused(rt):
             h.close()
 
 
-def test_backward_refuses_a_sky(rt):
-    s = scenegen.tiny_scene(33, n_spheres=4, n_lights=1)
-    cam = Camera()
-    W, H, D = 32, 24, 1
-    g = torch.ones((H, W, 3), device="cuda")
-    grads = {"albedo": torch.empty((4, 3), device="cuda")}
-    with rt.SceneHandle(s) as h:
-        rt.rt_scene_set_sky(h.handle, scenegen.sky_map(w=16, h=8))
-        with pytest.raises(rt.RtError) as e:
-            rt.rt_render_backward(h.handle, cam, W, H, D, g, grads)
-        assert e.value.status == rt.RT_ERR_UNSUPPORTED
-        rt.rt_scene_set_sky(h.handle, None)
-        rt.rt_render_backward(h.handle, cam, W, H, D, g, grads)
-        torch.cuda.synchronize()
-        assert torch.isfinite(grads["albedo"]).all()
-
-
 @pytest.mark.parametrize("mw,mh", [(1, 1), (1, 7), (9, 1), (2, 2)])
 def test_degenerate_maps(rt, oracle_mod, mw, mh):
     """Maps one texel wide or high: the wrap and the clamp fold onto the same
