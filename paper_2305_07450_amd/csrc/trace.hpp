@@ -577,7 +577,7 @@ __device__ __forceinline__ void transposed_shadow(float ocx, float ocy, float oc
     const bool in = mine & (ff <= r2) & (base + lane != selfq);
     const float sq = fsqrt(in ? r2 - ff : 0.0f);
     const float t0 = -b - sq, t1 = -b + sq;
-    const bool hit = in && ((t0 > 0.0f && t0 < limq) || (t1 > 0.0f && t1 < limq));
+    const bool hit = in & (((t0 > 0.0f) & (t0 < limq)) | ((t1 > 0.0f) & (t1 < limq)));
     const uint64_t h = wave_mask(hit);
     if (h) {
       const bool me = lane == q;
@@ -694,9 +694,9 @@ __device__ __forceinline__ void shadow_sphere_oc(float ocx, float ocy, float ocz
   if (wave_any(in)) {
     float sq = fsqrt(in ? r2 - ff : 0.0f);
     float t0 = -b - sq, t1 = -b + sq;
-    const bool hit = in && ((t0 > 0.0f && t0 < lim) || (t1 > 0.0f && t1 < lim));
+    const bool hit = in & (((t0 > 0.0f) & (t0 < lim)) | ((t1 > 0.0f) & (t1 < lim)));
     first = hit ? i : first;
-    occ = occ || hit;
+    occ = occ | hit;
   }
 }
 __device__ __forceinline__ void shadow_sphere(float4 g, int i, const Ray& rr, float lim, int self,
@@ -707,9 +707,9 @@ __device__ __forceinline__ void shadow_sphere(float4 g, int i, const Ray& rr, fl
   if (wave_any(in)) {
     float sq = fsqrt(in ? g.w - ff : 0.0f);
     float t0 = -b - sq, t1 = -b + sq;
-    const bool hit = in && ((t0 > 0.0f && t0 < lim) || (t1 > 0.0f && t1 < lim));
+    const bool hit = in & (((t0 > 0.0f) & (t0 < lim)) | ((t1 > 0.0f) & (t1 < lim)));
     first = hit ? i : first;
-    occ = occ || hit;
+    occ = occ | hit;
   }
 }
 
@@ -828,9 +828,12 @@ __device__ __forceinline__ bool occluded(const SceneDev& s, int l, float4 q, con
   sr.ox = f.px; sr.oy = f.py; sr.oz = f.pz;
   sr.dx = lx; sr.dy = ly; sr.dz = lz;
   for (int j = 0; j < s.n_planes; ++j) {
-    const bool hit = !occ && s.n_spheres + j != self && plane_root(ld4(s.pgeom, j), sr, s.t_min) < dist;
+    // computed by every lane and combined bitwise: a short-circuit here
+    // becomes an exec-mask branch around the root, which cost more
+    const float tp = plane_root(ld4(s.pgeom, j), sr, s.t_min);
+    const bool hit = (!occ) & (s.n_spheres + j != self) & (tp < dist);
     plane_hit = hit ? j : plane_hit;
-    occ = occ || hit;
+    occ = occ | hit;
   }
   if (act) {
     if (by_sphere)
