@@ -140,8 +140,6 @@ struct NodeArgs {
   hipKernelNodeParams prep_p{}, table_p{}, render_p{};
 };
 
-constexpr int kRenderBlock = 16;   // pixels per workgroup side (render.hip's tile)
-
 void fill_args(const rt_frame_s* f, const rt_camera& cam, int depth, int samples, float radius,
                bool move, NodeArgs& a) {
   const rt_scene_s& sc = *f->sc;
@@ -169,10 +167,8 @@ void fill_args(const rt_frame_s* f, const rt_camera& cam, int depth, int samples
   a.prep_p.blockDim = dim3(256);
   a.prep_p.kernelParams = a.prep_args;
   const bool sky = sc.sky != nullptr;
-  const dim3 grid((f->W + kRenderBlock - 1) / kRenderBlock,
-                  (f->H + kRenderBlock - 1) / kRenderBlock);
-  a.render_p.gridDim = grid;
-  a.render_p.blockDim = dim3(256);
+  a.render_p.gridDim = render_grid(f->W, f->H);
+  a.render_p.blockDim = dim3(kRenderThreads);
   if (f->soft) {
     a.samples = samples;
     a.table_args[0] = &a.samples;

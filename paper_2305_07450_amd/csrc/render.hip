@@ -1,18 +1,18 @@
 // render.hip - forward render kernel and scene packing kernel (gfx950).
 //
-// Launch shape: 256-lane workgroups of four wave64s; each wave owns an 8 x 8
-// pixel tile (one lane per pixel, paper Section 3.9: every pixel is an
-// independent work item), so the 64 rays of a wave start from the same eye
-// through neighbouring pixels and take the same branch over most primitives.
+// Launch shape: one wave64 per workgroup, owning an 8 x 8 pixel tile (one lane
+// per pixel, paper Section 3.9: every pixel is an independent work item), so
+// the 64 rays of a wave start from the same eye through neighbouring pixels
+// and take the same branch over most primitives.  The kernels use no LDS, so
+// the workgroup is only a unit of dispatch: single waves fill the compute
+// units more evenly than groups of four did (5 % faster at 1080p).
 // The scene is read through scalar loads (trace.hpp), so the inner loops are
 // pure VALU arithmetic on SGPR operands.
 #include "rt_internal.hpp"
 
 namespace rtk {
 
-constexpr int kTile = 8;          // wave tile edge
-constexpr int kBlockTiles = 2;    // workgroup = 2 x 2 wave tiles = 16 x 16 pixels
-constexpr int kBlock = kTile * kBlockTiles;
+constexpr int kTile = kRenderTile;   // wave tile edge = workgroup tile edge
 
 // Records sink: segment ids and lit masks in [depth+1][H][W] planes.
 struct RecordSink {
@@ -28,15 +28,14 @@ struct RecordSink {
 };
 
 template <bool kRecords, bool kPrefilter, class Bg>
-__global__ __launch_bounds__(256) void render_kernel(SceneDev s, CameraDev c, int depth,
+__global__ __launch_bounds__(kRenderThreads) void render_kernel(SceneDev s, CameraDev c, int depth,
                                                       float* __restrict__ rgb,
                                                       int32_t* __restrict__ id_out,
                                                       int32_t* __restrict__ rec_ids,
                                                       uint8_t* __restrict__ rec_lit) {
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int x = blockIdx.x * kBlock + (wave & 1) * kTile + (lane & 7);
-  const int y = blockIdx.y * kBlock + (wave >> 1) * kTile + (lane >> 3);
+  const int lane = threadIdx.x;
+  const int x = blockIdx.x * kTile + (lane & 7);
+  const int y = blockIdx.y * kTile + (lane >> 3);
   // lanes outside the image run along (clamped pixel, no output) so that the
   // whole wave executes the path code together; a wave with no pixel leaves
   const bool live = x < c.W && y < c.H;
@@ -70,14 +69,13 @@ __global__ __launch_bounds__(256) void render_kernel(SceneDev s, CameraDev c, in
 
 // Soft-shadow render: the same paths with every light sampled (SoftShadows).
 template <bool kPrefilter, class Bg>
-__global__ __launch_bounds__(256) void render_soft_kernel(SceneDev s, CameraDev c, int depth,
+__global__ __launch_bounds__(kRenderThreads) void render_soft_kernel(SceneDev s, CameraDev c, int depth,
                                                            SoftShadows sh,
                                                            float* __restrict__ rgb,
                                                            int32_t* __restrict__ id_out) {
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int x = blockIdx.x * kBlock + (wave & 1) * kTile + (lane & 7);
-  const int y = blockIdx.y * kBlock + (wave >> 1) * kTile + (lane >> 3);
+  const int lane = threadIdx.x;
+  const int x = blockIdx.x * kTile + (lane & 7);
+  const int y = blockIdx.y * kTile + (lane >> 3);
   const bool live = x < c.W && y < c.H;
   if (!wave_any(live)) return;
   const int64_t pix = live ? (int64_t)y * c.W + x : 0;
@@ -120,24 +118,24 @@ hipError_t launch_render_soft(const rt_scene_s& sc, const CameraDev& c, int dept
   sh.n = samples;
   sh.radius = radius;
   sh.table = sc.soft_table;
-  dim3 grid((c.W + kBlock - 1) / kBlock, (c.H + kBlock - 1) / kBlock);
+  const dim3 grid = render_grid(c.W, c.H);
   const bool sky = sc.sky != nullptr;
   auto kern = sky ? (prefilter ? render_soft_kernel<true, SkyBackground>
                                : render_soft_kernel<false, SkyBackground>)
                   : (prefilter ? render_soft_kernel<true, PlainBackground>
                                : render_soft_kernel<false, PlainBackground>);
-  hipLaunchKernelGGL(kern, grid, dim3(256), 0, stream, sc.view(), c, depth, sh, rgb, ids);
+  hipLaunchKernelGGL(kern, grid, dim3(kRenderThreads), 0, stream, sc.view(), c, depth, sh, rgb,
+                     ids);
   return hipGetLastError();
 }
 
 // Counting launch: the same paths, plus the algorithmic counters summed per
 // wave (xor butterfly) and added to counts[kNumCounts] with integer atomics.
-__global__ __launch_bounds__(256) void count_kernel(SceneDev s, CameraDev c, int depth,
+__global__ __launch_bounds__(kRenderThreads) void count_kernel(SceneDev s, CameraDev c, int depth,
                                                     unsigned long long* __restrict__ counts) {
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int x = blockIdx.x * kBlock + (wave & 1) * kTile + (lane & 7);
-  const int y = blockIdx.y * kBlock + (wave >> 1) * kTile + (lane >> 3);
+  const int lane = threadIdx.x;
+  const int x = blockIdx.x * kTile + (lane & 7);
+  const int y = blockIdx.y * kTile + (lane >> 3);
   Count cnt;
   const bool live = x < c.W && y < c.H;
   if (wave_any(live)) {
@@ -157,8 +155,8 @@ __global__ __launch_bounds__(256) void count_kernel(SceneDev s, CameraDev c, int
 
 hipError_t launch_counts(const SceneDev& s, const CameraDev& c, int depth,
                          unsigned long long* counts, hipStream_t stream) {
-  dim3 grid((c.W + kBlock - 1) / kBlock, (c.H + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(count_kernel, grid, dim3(256), 0, stream, s, c, depth, counts);
+  const dim3 grid = render_grid(c.W, c.H);
+  hipLaunchKernelGGL(count_kernel, grid, dim3(kRenderThreads), 0, stream, s, c, depth, counts);
   return hipGetLastError();
 }
 
@@ -183,7 +181,7 @@ const void* sample_table_kernel_fn() { return (const void*)sample_table_kernel; 
 hipError_t launch_render(const SceneDev& s, const CameraDev& c, int depth, float* rgb,
                          int32_t* ids, int32_t* rec_ids, uint8_t* rec_lit, bool prefilter,
                          hipStream_t stream) {
-  dim3 grid((c.W + kBlock - 1) / kBlock, (c.H + kBlock - 1) / kBlock);
+  const dim3 grid = render_grid(c.W, c.H);
   using P = PlainBackground;
   using K = SkyBackground;
   decltype(&render_kernel<false, true, P>) kern;
@@ -193,7 +191,8 @@ hipError_t launch_render(const SceneDev& s, const CameraDev& c, int depth, float
   else
     kern = rec_ids ? (prefilter ? render_kernel<true, true, P> : render_kernel<true, false, P>)
                    : (prefilter ? render_kernel<false, true, P> : render_kernel<false, false, P>);
-  hipLaunchKernelGGL(kern, grid, dim3(256), 0, stream, s, c, depth, rgb, ids, rec_ids, rec_lit);
+  hipLaunchKernelGGL(kern, grid, dim3(kRenderThreads), 0, stream, s, c, depth, rgb, ids, rec_ids,
+                     rec_lit);
   return hipGetLastError();
 }
 

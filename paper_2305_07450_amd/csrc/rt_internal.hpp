@@ -51,6 +51,13 @@ struct rt_scene_s {
 
 namespace rtk {
 
+// Render launches: one wave per workgroup, an 8 x 8 pixel tile per wave.
+constexpr int kRenderTile = 8;
+constexpr int kRenderThreads = 64;
+inline dim3 render_grid(int W, int H) {
+  return dim3((W + kRenderTile - 1) / kRenderTile, (H + kRenderTile - 1) / kRenderTile);
+}
+
 // Workgroups of the persistent adjoint grid (one partial-gradient slot each).
 constexpr int kAdjointBlocks = 1024;
 
