@@ -138,10 +138,12 @@ __device__ __forceinline__ float root_of(const SceneDev& s, const Ray& r, int id
   return plane_root(ld4(s.pgeom, id - s.n_spheres), r, s.t_min);
 }
 
-// Sink that keeps the decisions of a re-traced path in registers.
+// Sink that keeps the decisions of a re-traced path in registers (kD: the
+// depth the arrays are sized for).
+template <int kD>
 struct RegRecords {
-  int ids[kMaxDepth + 1];
-  uint32_t lits[kMaxDepth + 1];
+  int ids[kD + 1];
+  uint32_t lits[kD + 1];
   __device__ __forceinline__ void seg(int k, int id) {
     ids[k] = id;
     lits[k] = 0;
@@ -157,7 +159,10 @@ __device__ __forceinline__ float dotv(V3 a, V3 b) { return dot3(a.x, a.y, a.z, b
 
 // kL: lights the per-lane light accumulators are sized for (a bound on the
 // scene's light count, so that a 1-light scene does not hold registers for 8).
-template <bool kHasRecords, int kL>
+// kD: the same for the depth.  Up to depth 4 the segment loops are unrolled
+// over kD, so the per-segment rays, throughputs and decisions sit in
+// registers at fixed indices instead of in private memory.
+template <bool kHasRecords, int kL, int kD>
 __global__ __launch_bounds__(256) void adjoint_kernel(SceneDev s, CameraDev c, int depth,
                                                        const float* __restrict__ grad_rgb,
                                                        const int32_t* __restrict__ rec_ids,
@@ -192,14 +197,15 @@ __global__ __launch_bounds__(256) void adjoint_kernel(SceneDev s, CameraDev c, i
       const int64_t pix = valid ? (int64_t)y * c.W + x : 0;
 
       // decisions of the path
-      RegRecords rr;
+      RegRecords<kD> rr;
       int K = 0;          // segments with a hit
       bool ends_in_miss = false;
       float gr = 0.f, gg = 0.f, gb = 0.f;
       if (!kHasRecords) {
         // re-trace with the forward kernel's code; lanes outside the image
         // run along (the path code needs the whole wave), without a path
-        for (int k = 0; k <= depth; ++k) rr.ids[k] = kNotTraced;
+#pragma unroll
+        for (int k = 0; k <= kD; ++k) rr.ids[k] = kNotTraced;
         if (wave_any(valid)) {
           float cr, cg, cb;
           int prim;
@@ -212,13 +218,17 @@ __global__ __launch_bounds__(256) void adjoint_kernel(SceneDev s, CameraDev c, i
         gg = grad_rgb[3 * pix + 1];
         gb = grad_rgb[3 * pix + 2];
         if (kHasRecords) {
-          for (int k = 0; k <= depth; ++k) {
+#pragma unroll
+          for (int k = 0; k <= kD; ++k) {
+            if (k > depth) break;
             rr.ids[k] = rec_ids[k * plane + pix];
             rr.lits[k] = rec_lit[k * plane + pix];
           }
         }
         const int n_prims = s.n_spheres + s.n_planes;
-        for (int k = 0; k <= depth; ++k) {
+#pragma unroll
+        for (int k = 0; k <= kD; ++k) {
+          if (k > depth) break;
           // ids outside the scene (records of another scene) end the path
           if (rr.ids[k] >= 0 && rr.ids[k] < n_prims) {
             K = k + 1;
@@ -231,14 +241,16 @@ __global__ __launch_bounds__(256) void adjoint_kernel(SceneDev s, CameraDev c, i
 
       // forward replay: ray and throughput of every hit segment, then those of
       // the segment after the last hit
-      Ray rays[kMaxDepth + 1];
-      float Ts[kMaxDepth + 1];
+      Ray rays[kD + 1];
+      float Ts[kD + 1];
       Ray r_end;
       float T_end;
       {
         Ray r = primary_ray(c, valid ? x : 0, valid ? y : 0);
         float T = 1.0f;
-        for (int k = 0; k < K; ++k) {
+#pragma unroll
+        for (int k = 0; k <= kD; ++k) {
+          if (k >= K) break;
           rays[k] = r;
           Ts[k] = T;
           const int id = rr.ids[k];
@@ -269,7 +281,9 @@ __global__ __launch_bounds__(256) void adjoint_kernel(SceneDev s, CameraDev c, i
           dbar.x *= T_end; dbar.y *= T_end; dbar.z *= T_end;
         }
       }
-      for (int k = depth; k >= 0; --k) {
+#pragma unroll
+      for (int k = kD; k >= 0; --k) {
+        if (k > depth) continue;
         // every lane runs the same k so that the wave-wide reductions below line up
         const bool active = valid && k < K;
         int sid = -1;
@@ -501,12 +515,20 @@ hipError_t launch_backward(const rt_scene_s& sc, const CameraDev& c, int depth,
   if (blocks > n_tiles) blocks = n_tiles;
   SceneDev s = sc.view();
   // the smallest light bucket that holds the scene's lights
-  auto pick = [&](auto with_records) {
+  // ... and depth bucket
+  auto pick_d = [&](auto with_records, auto lights) {
     constexpr bool kRec = decltype(with_records)::value;
-    if (L <= 1) return adjoint_kernel<kRec, 1>;
-    if (L <= 2) return adjoint_kernel<kRec, 2>;
-    if (L <= 4) return adjoint_kernel<kRec, 4>;
-    return adjoint_kernel<kRec, kMaxLights>;
+    constexpr int kLb = decltype(lights)::value;
+    if (depth <= 1) return adjoint_kernel<kRec, kLb, 1>;
+    if (depth <= 2) return adjoint_kernel<kRec, kLb, 2>;
+    if (depth <= 4) return adjoint_kernel<kRec, kLb, 4>;
+    return adjoint_kernel<kRec, kLb, kMaxDepth>;
+  };
+  auto pick = [&](auto with_records) {
+    if (L <= 1) return pick_d(with_records, std::integral_constant<int, 1>{});
+    if (L <= 2) return pick_d(with_records, std::integral_constant<int, 2>{});
+    if (L <= 4) return pick_d(with_records, std::integral_constant<int, 4>{});
+    return pick_d(with_records, std::integral_constant<int, kMaxLights>{});
   };
   auto kern = rec_ids ? pick(std::true_type{}) : pick(std::false_type{});
   hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * waves), lds, stream, s, c, depth, grad_rgb,
