@@ -6,9 +6,11 @@
  * pinhole primary rays (paper Sections 3.1-3.3), brute-force closest hit
  * over every primitive (Section 3.4.1), Phong or Blinn-Phong shading
  * (Section 3.5) with hard cast shadows (Section 3.6), and mirror
- * reflections up to a fixed bounce limit (Section 3.7).  It also gives the
- * adjoint of that image with visibility held fixed, and a batched launch of
- * many scenes.
+ * reflections up to a fixed bounce limit (Section 3.7).  Around that: soft
+ * shadows of spherical lights (Section 3.6.1), a skybox (Section 3.8), the
+ * adjoint of the image with visibility held fixed, a batched launch of many
+ * scenes, and an interactive per-frame path that streams camera, settings
+ * and body positions in and the image out (Section 3.9).
  *
  * Conventions for every call:
  *   - All calls are C, never throw, and return rt_status.  On failure a
@@ -19,8 +21,8 @@
  *     Work is asynchronous on that stream; a device fault surfaces at a later
  *     call or synchronisation as RT_ERR_DEVICE.
  *   - Pointers named *_out, records and gradients are caller-owned device
- *     memory.  rt_scene and rt_batch objects are library-owned and freed by
- *     their destroy call.
+ *     memory.  rt_scene, rt_batch and rt_frame objects are library-owned and
+ *     freed by their destroy call.
  *   - Images are row-major, row 0 at the top: element (y, x) of a W x H image
  *     is at index y * W + x (the paper's pixel index, Section 3.9).
  *   - Camera frame: x right, y up, the camera looks down -z; yaw turns about

@@ -128,6 +128,7 @@ struct NodeArgs {
   CameraDev c{};
   int depth = 0;
   int samples = 0;
+  float radius = 0.0f;
   float2* table = nullptr;
   SoftShadows sh{};
   float* rgb = nullptr;
@@ -135,7 +136,7 @@ struct NodeArgs {
   int32_t* rec_ids = nullptr;
   uint8_t* rec_lit = nullptr;
   void* prep_args[1];
-  void* table_args[2];
+  void* table_args[3];
   void* render_args[7];
   hipKernelNodeParams prep_p{}, table_p{}, render_p{};
 };
@@ -171,9 +172,11 @@ void fill_args(const rt_frame_s* f, const rt_camera& cam, int depth, int samples
   a.render_p.blockDim = dim3(kRenderThreads);
   if (f->soft) {
     a.samples = samples;
-    a.table_args[0] = &a.samples;
+    a.radius = radius;
     a.table = sc.soft_table;
-    a.table_args[1] = &a.table;
+    a.table_args[0] = &a.samples;   // sample_table_kernel(int n, float radius, float2* table)
+    a.table_args[1] = &a.radius;
+    a.table_args[2] = &a.table;
     a.table_p.func = (void*)sample_table_kernel_fn();
     a.table_p.gridDim = dim3((samples + 255) / 256);
     a.table_p.blockDim = dim3(256);

@@ -93,17 +93,17 @@ __global__ __launch_bounds__(kRenderThreads) void render_soft_kernel(SceneDev s,
   }
 }
 
-// Sample points of the sunflower arrangement in units of the light radius:
-// point i of n at radius 2 sqrt(i/n) and angle i times the golden angle
-// pi (3 - sqrt 5), as (x, y) in the disk basis; computed in double and
-// rounded once.
-__global__ void sample_table_kernel(int n, float2* __restrict__ table) {
+// Sample points of the sunflower arrangement: point i of n at radius
+// 2 sqrt(i/n) and angle i times the golden angle pi (3 - sqrt 5), as (x, y)
+// in the disk basis, computed in double and rounded once, then times the
+// light radius in FP32 (so the render reads the offsets ready to use).
+__global__ void sample_table_kernel(int n, float radius, float2* __restrict__ table) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
     const double golden = 3.14159265358979323846 * (3.0 - sqrt(5.0));
     const double r = 2.0 * sqrt((double)i / (double)n);
     const double th = (double)i * golden;
-    table[i] = make_float2((float)(r * cos(th)), (float)(r * sin(th)));
+    table[i] = make_float2(radius * (float)(r * cos(th)), radius * (float)(r * sin(th)));
   }
 }
 
@@ -111,7 +111,7 @@ hipError_t launch_render_soft(const rt_scene_s& sc, const CameraDev& c, int dept
                               float radius, float* rgb, int32_t* ids, bool prefilter,
                               hipStream_t stream) {
   hipLaunchKernelGGL(sample_table_kernel, dim3((samples + 255) / 256), dim3(256), 0, stream,
-                     samples, sc.soft_table);
+                     samples, radius, sc.soft_table);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   SoftShadows sh;

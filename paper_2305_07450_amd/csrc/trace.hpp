@@ -919,9 +919,9 @@ struct SoftShadows {
   static constexpr bool kSoft = true;
   int n;                // samples per light
   float radius;         // light radius R
-  const float2* table;  // [n, rounded up to 8]: sample i in units of R in the
-                        // disk basis, 2 sqrt(i/n) (cos(i phi), sin(i phi)), phi the
-                        // golden angle; 64-byte aligned
+  const float2* table;  // [n, rounded up to 8]: sample i in the disk basis,
+                        // R times the FP32 rounding of 2 sqrt(i/n) (cos(i phi),
+                        // sin(i phi)), phi the golden angle; 64-byte aligned
 };
 
 // Chunks of 64 spheres whose candidate masks a soft-shadow bound keeps; a
@@ -1053,7 +1053,7 @@ __device__ __forceinline__ float soft_visibility(const SceneDev& s, float4 q, co
 #pragma unroll
       for (int k = 0; k < kSoftGroup; ++k) {
         const int kk = k0 + k;
-        const float u = sh.radius * tb[2 * kk], v = sh.radius * tb[2 * kk + 1];
+        const float u = tb[2 * kk], v = tb[2 * kk + 1];   // already times the radius
         float x = fmaf(u, ax, fmaf(v, bx, q.x)) - f.px;
         float y = fmaf(u, ay, fmaf(v, by, q.y)) - f.py;
         float z = fmaf(u, az, fmaf(v, bz, q.z)) - f.pz;
@@ -1085,12 +1085,14 @@ __device__ __forceinline__ float soft_visibility(const SceneDev& s, float4 q, co
         for (int j = 0; j < s.n_planes; ++j) {
           const float4 pg = ld4(s.pgeom, j);
           const bool other = s.n_spheres + j != self;
+          // plane_root with the origin term, the same for every sample ray of
+          // the lane, formed once
+          const float num = pg.w - dot3(pg.x, pg.y, pg.z, f.px, f.py, f.pz);
 #pragma unroll
           for (int k = 0; k < kSoftGroup; ++k) {
-            Ray sr;
-            sr.ox = f.px; sr.oy = f.py; sr.oz = f.pz;
-            sr.dx = dx[k]; sr.dy = dy[k]; sr.dz = dz[k];
-            blk[k] = blk[k] | (other & (plane_root(pg, sr, tmin) < di[k]));
+            const float den = dot3(pg.x, pg.y, pg.z, dx[k], dy[k], dz[k]);
+            const float t = num * __builtin_amdgcn_rcpf(den);
+            blk[k] = blk[k] | (other & (den != 0.0f) & (t > tmin) & (t < di[k]));
           }
         }
       }
