@@ -525,7 +525,7 @@ __device__ __forceinline__ bool sphere_may_meet(const WaveBundle& b, float4 g, f
 // kTransShadowCost in a shadow test, against about kLaneHitCost and
 // kLaneShadowCost per candidate sphere in the per-lane loops.
 constexpr int kTransHitCost = 45, kLaneHitCost = 20;
-constexpr int kTransShadowCost = 30, kLaneShadowCost = 10;
+constexpr int kTransShadowCost = 20, kLaneShadowCost = 10;
 constexpr bool kTransposedHit = true, kTransposedShadow = true;
 
 // Nearest root over the spheres base + j (j in `cand`, geometry g in lane j)
