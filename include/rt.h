@@ -227,8 +227,9 @@ rt_status rt_render_counts(rt_scene scene, const rt_camera* cam, int32_t W, int3
  * rt_render for the same scene, camera, size and depth.  The sum over pixels
  * is deterministic (fixed order, no floating-point atomics).  With a skybox,
  * a path that ends in a miss also feeds its last mirror direction through
- * the UV mapping and the bilinear weights (texels are constants).  No
- * allocation; capture-safe. */
+ * the UV mapping and the bilinear weights (texels are constants).  Scenes of
+ * more than 2335 spheres (the per-wave gradient accumulators must fit in
+ * LDS) return RT_ERR_UNSUPPORTED.  No allocation; capture-safe. */
 rt_status rt_render_backward(rt_scene scene, const rt_camera* cam, int32_t W, int32_t H,
                              int32_t depth, const float* grad_rgb, const rt_records* rec,
                              const rt_grads* grads, void* stream);
