@@ -285,3 +285,34 @@ def test_frames_of_small_and_empty_scenes(rt):
                     assert np.array_equal(px, argb8(want.numpy())), (name, k)
             finally:
                 rt.rt_frame_destroy(f)
+
+
+@pytest.mark.parametrize("soft", [False, True])
+def test_frames_without_prefilters(rt, soft):
+    """A frame object made with RT_RENDER_NO_PREFILTER renders what the eager
+    calls render with that flag, which is also the image with the bounds."""
+    s = scenegen.paper_scene()
+    W, H = 96, 54
+    motion = scenegen.verlet_motion(s, 3, seed=4)
+    n, D = scenegen.PAPER_SETTINGS["soft200_3bounces" if soft else "hard_1bounce"]
+    n = n if soft else 1
+    R = scenegen.PAPER_LIGHT_RADIUS if soft else 0.0
+    out = torch.empty((H, W, 3), device="cuda")
+    with rt.SceneHandle(s) as hf, rt.SceneHandle(s) as he:
+        f = rt.rt_frame_create(hf.handle, W, H, out, soft=soft, flags=rt.RT_RENDER_NO_PREFILTER)
+        try:
+            for k in range(3):
+                rt.rt_frame_submit(f, orbit(k), D, n, R, motion[k])
+                rt.rt_frame_result(f)
+                got = out.cpu()
+                rt.rt_scene_update(he.handle, moved(s, motion[k]))
+                ref = torch.empty((H, W, 3), device="cuda")
+                for flags in (rt.RT_RENDER_NO_PREFILTER, 0):
+                    if soft:
+                        rt.rt_render_soft(he.handle, orbit(k), W, H, D, n, R, ref, None, flags)
+                    else:
+                        rt.rt_render_ex(he.handle, orbit(k), W, H, D, ref, None, None, flags)
+                    torch.cuda.synchronize()
+                    assert torch.equal(got, ref.cpu()), (k, flags)
+        finally:
+            rt.rt_frame_destroy(f)
