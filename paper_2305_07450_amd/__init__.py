@@ -30,6 +30,7 @@ RT_RENDER_NO_PREFILTER = 1
 RT_MAX_SAMPLES = 4096
 RT_MAX_SKY_DIM = 16384
 RT_MAX_DIM = 16384
+RT_MAX_BATCH = 4096
 RT_FRAME_RGB32F, RT_FRAME_ARGB8 = 0, 1
 
 if not os.path.exists(LIB_PATH):

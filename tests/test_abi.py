@@ -36,6 +36,19 @@ def test_header_declares_the_entry_points():
         assert s in syms
 
 
+def test_binding_constants_match_the_header(rt):
+    """Every numeric #define and enum value of include/rt.h has a constant of
+    the same name and value in the Python binding."""
+    text = open(os.path.join(ROOT, "include", "rt.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    consts = {m[0]: int(m[1]) for m in re.findall(r"^#define\s+(RT_\w+)\s+(\d+)[uU]?\s*$", text,
+                                                  flags=re.M)}
+    consts.update({m[0]: int(m[1]) for m in re.findall(r"\b(RT_[A-Z0-9_]+)\s*=\s*(\d+)", text)})
+    assert len(consts) >= 20, sorted(consts)
+    for name, value in consts.items():
+        assert getattr(rt, name, None) == value, name
+
+
 def test_library_exports_every_declared_symbol(rt):
     lib = C.CDLL(rt.LIB_PATH)
     missing = [s for s in declared_symbols() if not hasattr(lib, s)]
