@@ -454,14 +454,17 @@ __global__ __launch_bounds__(256) void adjoint_kernel(SceneDev s, CameraDev c, i
 }
 
 // Sum the workgroup partials and scatter to the caller's arrays.  A workgroup
-// owns 64 consecutive entries; its four waves add every fourth partial (rows
-// b = w, w + 4, ...; one coalesced 256-byte row read per wave per step), then
-// wave 0 adds the four wave sums in wave order.  The order is fixed, so the
-// result does not depend on timing.
+// owns 64 consecutive entries; its sixteen waves add every sixteenth partial
+// (rows b = w, w + 16, ...; one coalesced 256-byte row read per wave per
+// step), then wave 0 adds the sixteen wave sums in wave order.  The order is
+// fixed, so the result does not depend on timing.  There are only about
+// (7N + 4L) / 64 workgroups, so the reads are latency bound: sixteen short
+// chains of rows per column group keep more of them in flight than four long
+// ones.
 constexpr int kReduceCols = 64;
-constexpr int kReduceWaves = 4;
+constexpr int kReduceWaves = 16;
 
-__global__ __launch_bounds__(256) void reduce_kernel(const float* __restrict__ partials,
+__global__ __launch_bounds__(64 * kReduceWaves) void reduce_kernel(const float* __restrict__ partials,
                                                       int stride, int blocks, int N, int L,
                                                       rt_grads g) {
   __shared__ float part[kReduceWaves][kReduceCols];
