@@ -152,7 +152,9 @@ rt_status rt_scene_update(rt_scene scene, const rt_scene_desc* desc, void* strea
  *         skybox.
  * Allocates the skybox's own device buffer when the scene has none of this
  * size (frees it on removal); not capture-safe.  With mem == RT_HOST the copy
- * is synchronous; with RT_DEVICE it is ordered on `stream`.  Renders already
+ * is synchronous, through a host staging buffer of 16 bytes per texel that is
+ * allocated first: if that fails, RT_ERR_OUT_OF_MEMORY and the scene's skybox
+ * is unchanged.  With RT_DEVICE it is ordered on `stream`.  Renders already
  * queued on other streams must be finished first. */
 rt_status rt_scene_set_sky(rt_scene scene, const float* rgb, int32_t w, int32_t h, rt_mem mem,
                            void* stream);
@@ -242,7 +244,11 @@ typedef struct rt_batch_s* rt_batch;
  * shape (autotuned once per problem signature when `autotune` is non-zero,
  * which runs and synchronises on `stream`; cached in memory), allocates the
  * queue counter and captures the graph.  rgb_out[i] is device float32
- * [H[i]][W[i]][3]. */
+ * [H[i]][W[i]][3].  Sizes, depths, cameras and the total tile count (at most
+ * 2^31 - 1 tiles of 64 pixels, the queue's 32-bit tile numbers) are checked
+ * before any scene is read: RT_ERR_INVALID_ARG.  A failed host or device
+ * allocation returns RT_ERR_OUT_OF_MEMORY or RT_ERR_DEVICE and leaves nothing
+ * allocated. */
 rt_status rt_batch_create(int32_t n, const rt_scene* scenes, const rt_camera* cams,
                           const int32_t* W, const int32_t* H, const int32_t* depth,
                           float* const* rgb_out, int32_t autotune, void* stream, rt_batch* out);

@@ -237,6 +237,17 @@ done:
   return st;
 }
 
+// Queue capacity for one image: the most tiles any candidate shape makes
+// (one-wave tiles).
+size_t most_tiles(int W, int H) {
+  size_t most = 0;
+  for (int ww : {8, 16, 64}) {
+    const int wh = 64 / ww;
+    most = std::max(most, (size_t)((W + ww - 1) / ww) * (size_t)((H + wh - 1) / wh));
+  }
+  return most;
+}
+
 void free_batch(rt_batch_s* b) {
   if (!b) return;
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
@@ -249,14 +260,17 @@ void free_batch(rt_batch_s* b) {
   delete b;
 }
 
-}  // namespace
+// Frees a batch under construction unless released: host allocations below
+// may throw, and the exported call turns that into an error code.
+struct BatchGuard {
+  rt_batch_s* b = nullptr;
+  ~BatchGuard() { free_batch(b); }
+};
 
-extern "C" {
-
-rt_status rt_batch_create(int32_t n, const rt_scene* scenes, const rt_camera* cams,
-                          const int32_t* W, const int32_t* H, const int32_t* depth,
-                          float* const* rgb_out, int32_t autotune_flag, void* stream_v,
-                          rt_batch* out) {
+rt_status batch_create(int32_t n, const rt_scene* scenes, const rt_camera* cams,
+                       const int32_t* W, const int32_t* H, const int32_t* depth,
+                       float* const* rgb_out, int32_t autotune_flag, void* stream_v,
+                       rt_batch* out) {
   if (!out) return err(RT_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
   if (n <= 0 || n > RT_MAX_BATCH)
@@ -277,15 +291,22 @@ rt_status rt_batch_create(int32_t n, const rt_scene* scenes, const rt_camera* ca
       return err(RT_ERR_INVALID_ARG, "image " + std::to_string(i) + " size out of range");
     if (depth[i] < 0 || depth[i] > RT_MAX_DEPTH)
       return err(RT_ERR_INVALID_ARG, "depth " + std::to_string(i) + " outside [0, 8]");
+  }
+  // the persistent kernel numbers the queue's tiles with 32-bit integers
+  size_t max_tiles = 0;
+  for (int i = 0; i < n; ++i) max_tiles += most_tiles(W[i], H[i]);
+  if (max_tiles > (size_t)INT32_MAX)
+    return err(RT_ERR_INVALID_ARG, "the batch makes " + std::to_string(max_tiles) +
+                                       " tiles, more than 2^31 - 1");
+  for (int i = 1; i < n; ++i)
     if (scenes[i]->device != scenes[0]->device)
       return err(RT_ERR_INVALID_ARG, "scenes live on different devices");
-  }
   hipStream_t stream = (hipStream_t)stream_v;
   rt_batch_s* b = new (std::nothrow) rt_batch_s();
   if (!b) return err(RT_ERR_OUT_OF_MEMORY, "host allocation failed");
+  BatchGuard guard{b};
   b->n = n;
   b->device = scenes[0]->device;
-  size_t max_tiles = 0;
   for (int i = 0; i < n; ++i) {
     BatchJob j;
     j.s = scenes[i]->view();
@@ -299,13 +320,6 @@ rt_status rt_batch_create(int32_t n, const rt_scene* scenes, const rt_camera* ca
     const rt_scene_s* sc = scenes[i];
     b->job_cost.push_back(64.0 * (depth[i] + 1) * (sc->n_spheres + sc->n_planes + 1) *
                           (1 + sc->n_lights));
-    // queue capacity: the most tiles any candidate shape makes (one-wave tiles)
-    size_t most = 0;
-    for (int ww : {8, 16, 64}) {
-      const int wh = 64 / ww;
-      most = std::max(most, (size_t)((W[i] + ww - 1) / ww) * (size_t)((H[i] + wh - 1) / wh));
-    }
-    max_tiles += most;
   }
   size_t total_spheres = 0;
   for (int i = 0; i < n; ++i) {
@@ -330,11 +344,7 @@ rt_status rt_batch_create(int32_t n, const rt_scene* scenes, const rt_camera* ca
   if (e == hipSuccess) e = hipMalloc(&b->jobs, sizeof(BatchJob) * n);
   if (e == hipSuccess) e = hipMalloc(&b->queue, sizeof(TileRef) * max_tiles);
   if (e == hipSuccess) e = hipMalloc(&b->counter, sizeof(unsigned int));
-  if (e != hipSuccess) {
-    rt_status st = hip_fail(e, "batch allocation");
-    free_batch(b);
-    return st;
-  }
+  if (e != hipSuccess) return hip_fail(e, "batch allocation");
   Shape sh{4, 8, cus * 4};
   rt_status st = RT_OK;
   if (autotune_flag) {
@@ -350,10 +360,7 @@ rt_status rt_batch_create(int32_t n, const rt_scene* scenes, const rt_camera* ca
     }
     if (!hit) {
       st = autotune(b, cus, stream, &sh);
-      if (st != RT_OK) {
-        free_batch(b);
-        return st;
-      }
+      if (st != RT_OK) return st;
       std::lock_guard<std::mutex> lk(g_tune_mu);
       g_tune_cache[key] = sh;
     }
@@ -370,13 +377,26 @@ rt_status rt_batch_create(int32_t n, const rt_scene* scenes, const rt_camera* ca
   }
   if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
   if (cap) (void)hipStreamDestroy(cap);
-  if (e != hipSuccess) {
-    st = hip_fail(e, "batch graph capture");
-    free_batch(b);
-    return st;
-  }
+  if (e != hipSuccess) return hip_fail(e, "batch graph capture");
+  guard.b = nullptr;
   *out = b;
   return RT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rt_status rt_batch_create(int32_t n, const rt_scene* scenes, const rt_camera* cams,
+                          const int32_t* W, const int32_t* H, const int32_t* depth,
+                          float* const* rgb_out, int32_t autotune_flag, void* stream_v,
+                          rt_batch* out) {
+  try {
+    return batch_create(n, scenes, cams, W, H, depth, rgb_out, autotune_flag, stream_v, out);
+  } catch (const std::bad_alloc&) {
+    if (out) *out = nullptr;
+    return err(RT_ERR_OUT_OF_MEMORY, "host allocation failed");
+  }
 }
 
 // The job descriptors hold each scene's skybox pointer and size as they were

@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <memory>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -301,6 +302,13 @@ rt_status rt_scene_set_sky(rt_scene sc, const float* rgb, int32_t w, int32_t h, 
   if (mem == RT_HOST && !finite_all(rgb, 3 * (int64_t)texels))
     return fail(RT_ERR_INVALID_ARG, "non-finite value in the skybox");
   hipStream_t st = (hipStream_t)stream;
+  // host staging (up to 4 GiB) before the scene changes: an allocation failure
+  // is reported, not thrown, and leaves the scene's skybox as it was
+  std::unique_ptr<float4[]> tex;
+  if (mem == RT_HOST) {
+    tex.reset(new (std::nothrow) float4[texels]);
+    if (!tex) return fail(RT_ERR_OUT_OF_MEMORY, "skybox staging: host allocation failed");
+  }
   if (sc->sky && (sc->sky_w != w || sc->sky_h != h)) {
     hipError_t e = hipFree(sc->sky);
     sc->sky = nullptr;
@@ -317,10 +325,9 @@ rt_status rt_scene_set_sky(rt_scene sc, const float* rgb, int32_t w, int32_t h, 
   sc->sky_w = w;
   sc->sky_h = h;
   if (mem == RT_HOST) {
-    std::vector<float4> tex(texels);
     for (size_t i = 0; i < texels; ++i)
       tex[i] = make_float4(rgb[3 * i], rgb[3 * i + 1], rgb[3 * i + 2], 0.0f);
-    HIP_TRY(hipMemcpyAsync(sc->sky, tex.data(), texels * sizeof(float4), hipMemcpyHostToDevice,
+    HIP_TRY(hipMemcpyAsync(sc->sky, tex.get(), texels * sizeof(float4), hipMemcpyHostToDevice,
                            st),
             "skybox upload");
     HIP_TRY(hipStreamSynchronize(st), "skybox upload sync");

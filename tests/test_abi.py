@@ -196,6 +196,30 @@ def test_frame_rejects_bad_arguments_before_any_device_call(rt):
     assert rt._lib.rt_frame_destroy(None) == 0
 
 
+def test_batch_rejects_bad_arguments_before_any_device_call(rt):
+    """rt_batch_create checks sizes, cameras and the total tile count before it
+    reads a scene: placeholder scene and image pointers are never followed."""
+    def create(n, W, H, depth=1, cam=Camera()):
+        scenes = (C.c_void_p * n)(*([FAKE_SCENE] * n))
+        cams = (rt.rt_camera * n)(*([rt.make_camera(cam)] * n))
+        arr = lambda v: (C.c_int32 * n)(*([v] * n))
+        outs = (C.c_void_p * n)(*([0x1000] * n))
+        b = C.c_void_p(0x1234)
+        st = rt._lib.rt_batch_create(n, scenes, cams, arr(W), arr(H), arr(depth), outs, 0, None,
+                                     C.byref(b))
+        assert not b.value
+        return st
+    assert create(0, 8, 8) == rt.RT_ERR_INVALID_ARG
+    assert create(rt.RT_MAX_BATCH + 1, 8, 8) == rt.RT_ERR_INVALID_ARG
+    assert create(2, rt.RT_MAX_DIM + 1, 8) == rt.RT_ERR_INVALID_ARG
+    assert create(2, 8, 8, depth=rt.RT_MAX_DEPTH + 1) == rt.RT_ERR_INVALID_ARG
+    assert create(2, 8, 8, cam=Camera(fov_deg=180.0)) == rt.RT_ERR_INVALID_ARG
+    # every size at its maximum: 4096 x 16384^2 pixels make about 1.7e10
+    # one-wave tiles, past the queue's 32-bit tile numbers
+    assert create(rt.RT_MAX_BATCH, rt.RT_MAX_DIM, rt.RT_MAX_DIM) == rt.RT_ERR_INVALID_ARG
+    assert "tiles" in rt.rt_last_error()
+
+
 def test_destroy_null_is_a_no_op(rt):
     assert rt._lib.rt_scene_destroy(None) == 0
 
