@@ -63,17 +63,16 @@ static void normalize3(double v[3]) {
 
 /* ---- Sections 3.2, 3.2.1 and 3.3: camera, viewport and primary rays ------ */
 
-/* The paper's NDC listing, branch for branch: the shorter window side spans
- * [-1, 1] and y grows downwards on the screen. */
+/* Section 3.2: the shorter window side spans [-1, 1] of the viewport and
+ * screen rows grow downwards.  A pixel's viewport coordinates are therefore
+ * its offset from the image centre (W/2, H/2), in units of half the shorter
+ * side, with the row offset negated so that up is positive.  The worked
+ * example of that section (the centre pixel of 1280x720 at the origin) has no
+ * half-pixel offset, and neither has this mapping. */
 static void ndc_coords(int32_t W, int32_t H, int32_t x, int32_t y, double* u, double* v) {
-  double width = (double)W, height = (double)H, px = (double)x, py = (double)y;
-  if (width > height) {
-    *u = (px - width / 2.0 + height / 2.0) / height * 2.0 - 1.0;
-    *v = -(py / height * 2.0 - 1.0);
-  } else {
-    *u = px / width * 2.0 - 1.0;
-    *v = -((py - height / 2.0 + width / 2.0) / width * 2.0 - 1.0);
-  }
+  double half_short = 0.5 * (double)(W < H ? W : H);
+  *u = ((double)x - 0.5 * (double)W) / half_short;
+  *v = (0.5 * (double)H - (double)y) / half_short;
 }
 
 void or_camera_ray(const or_camera* cam, int32_t W, int32_t H, int32_t x, int32_t y,
@@ -324,6 +323,10 @@ typedef struct {
   int64_t pixel;
 } trace_ctx;
 
+/* SplitMix64 (Steele, Lea and Flood, "Fast Splittable Pseudorandom Number
+ * Generators", OOPSLA 2014), with the increment and the two multipliers of
+ * its published 64-bit finaliser.  It only seeds the jitter of the
+ * conditioning re-traces, never a rendered value. */
 static uint64_t splitmix64(uint64_t z) {
   z += 0x9E3779B97F4A7C15ull;
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;

@@ -139,3 +139,67 @@ def test_half_disk_occluder_halves_light(oracle_mod):
     nl = (qq - p)[1] / np.linalg.norm(qq - p)
     vis = (r.rgb[0] / a - float(s.ambient)) / nl
     assert abs(vis[0] - 0.5) < 0.06, vis
+
+
+def _angle_law_count(n, R, alpha, delta, law):
+    """Samples blocked by the half-space m.x < m.p - delta (m at angle alpha
+    from the disk's first axis towards its second, both horizontal here),
+    counted by hand from the sunflower law: point i at radius 2 R sqrt(i/n)
+    and angle theta(i) = i x 137.507 degrees, the golden angle as the paper
+    prints it.  `law` names the intended law or a plausible mistake."""
+    blocked = 0
+    for i in range(n):
+        r = 2.0 * R * math.sqrt(i / n)
+        th = {"printed": math.radians(i * 137.507),
+              "radians": i * 137.507,                      # degrees read as radians
+              "flipped": -math.radians(i * 137.507)}.get(law, math.radians(i * 137.507))
+        if law == "swapped":                              # the two disk axes swapped
+            along = r * (math.sin(th) * math.cos(alpha) + math.cos(th) * math.sin(alpha))
+        else:
+            along = r * (math.cos(th) * math.cos(alpha) + math.sin(th) * math.sin(alpha))
+        blocked += along < -delta
+    return blocked
+
+
+@pytest.mark.parametrize("n,alpha_deg,want", [(23, 330.0, 11), (16, 270.0, 7), (22, 215.0, 10)])
+def test_golden_angle_law_exact_count(oracle_mod, n, alpha_deg, want):
+    """The angle law theta(i) = i phi pinned by an exact count.  The light is
+    straight above the shaded ground point p, so the disk of samples is
+    horizontal, with first axis +x and second axis -z (the orthonormal basis
+    of Duff et al. for the up direction).  A vertical occluding plane with
+    horizontal normal m at angle alpha from the first axis, at distance delta
+    from p on the far side, blocks exactly the samples s with m.(s - q) <
+    -delta: the shadow ray from p runs from one side of the plane to the
+    other.  The camera and p lie on the same side of the wall.  The count
+    follows by hand from the printed golden angle; degrees read as radians, a
+    flipped angle and swapped axes each give another count, so each would
+    fail."""
+    R, delta = 1.0, 0.15
+    alpha = math.radians(alpha_deg)
+    cam = Camera()
+    W, H = 64, 36
+    pix = pixel_of(cam, W, H, (0.0, -1.0, -10.0))
+    p = plane_point(oracle_mod, cam, W, H, pix)
+    q = p + np.array([0.0, 6.0, 0.0])
+    # the disk axes for w = +y: e1 = +x, e2 = -z, so m in world coordinates
+    # is cos(alpha) e1 + sin(alpha) e2
+    m = np.array([math.cos(alpha), 0.0, -math.sin(alpha)])
+    wall = [m[0], m[1], m[2], float(m @ p) - delta]
+    s = scene_with([], [(*q, 1.0)], plane=False)
+    s = Scene(sphere_geom=np.zeros((0, 4), F32), sphere_mat=np.zeros((0, 4), F32),
+              sphere_shine=np.zeros(0, F32),
+              plane_geom=np.array([scenegen.GROUND[0], wall], F32),
+              plane_mat=np.array([[0.8, 0.6, 0.4, 0.0], [0.2, 0.2, 0.2, 0.0]], F32),
+              plane_shine=np.full(2, 16, F32), light=s.light, ambient=s.ambient,
+              spec_strength=F32(0.0))
+    want_by_hand = _angle_law_count(n, R, alpha, delta, "printed")
+    assert want_by_hand == want
+    for wrong in ("radians", "flipped", "swapped"):
+        assert _angle_law_count(n, R, alpha, delta, wrong) != want, wrong
+    r = oracle_mod.render(s, cam, W, H, 0, pixels=np.array([pix]), samples=n, light_radius=R)
+    assert r.prim_id[0] == 0     # the ground plane, seen in front of the wall
+    a = s.plane_mat[0, :3].astype(float)
+    qq = s.light[0, :3].astype(float)
+    nl = (qq - p)[1] / np.linalg.norm(qq - p)
+    vis = (r.rgb[0] / a - float(s.ambient)) / nl
+    np.testing.assert_allclose(vis, (n - want) / n, rtol=0, atol=1e-9)
