@@ -3,12 +3,17 @@
 
 A step is one rt_render of the 1920x1080 workload (64 spheres + ground plane,
 2 point lights, reflection depth 4, one primary ray per pixel, seeded
-synthetic scene): primary rays, closest hits, shading with shadow rays and the
-mirror bounces of every pixel.  The scene is resident in HBM before timing
-starts; the image stays in HBM.
+synthetic scene): the eye-cone launch, then the render kernel (primary rays,
+closest hits, shading with shadow rays and the mirror bounces of every
+pixel).  The scene is resident in HBM before timing starts; the image stays
+in HBM.
 
-Prints one JSON line: primary Mrays/s (value), fps, total Mrays/s, the FP32
-ALU roofline of the render kernel and the FP64 CPU oracle timed on the host.
+Prints one JSON line: primary Mrays/s (value), fps, total Mrays/s, the frame
+time distribution (mean, median, the paper's mean of 10 consecutive frames),
+the FP32 ALU roofline of the render kernel from the exact tests it executes,
+the brute-force variant (no culling) with its own fraction, the batched and
+forward+backward workloads, and the FP64 CPU oracle timed on the host beside
+the parity statistics of the headline frame.
 """
 
 from __future__ import annotations
@@ -24,38 +29,83 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3         # MI355X vector FP32 (packed), 256 CU x 256 FLOP/clk x 2.4 GHz
-PEAK_FP32_NONPACKED = 78.6       # 256 CU x 128 FLOP/clk x 2.4 GHz (no packed FP32 issued)
 FLOP_SPHERE_TEST = 16            # oc 3, b 5, |oc|^2 5, -r^2 1, b^2 - q 2 (FMA = 2)
 FLOP_PLANE_TEST = 12             # m.d 5, h - m.o 6, divide 1
+
+
+def test_flops(counts, executed: bool) -> int:
+    """FLOPs of the ray-primitive tests: the ones the kernel executed, or the
+    method's algorithmic count (every segment every primitive)."""
+    if executed:
+        return (FLOP_SPHERE_TEST * counts["exec_sphere_tests"]
+                + FLOP_PLANE_TEST * counts["exec_plane_tests"])
+    return FLOP_SPHERE_TEST * counts["sphere_tests"] + FLOP_PLANE_TEST * counts["plane_tests"]
+
+
+def frac_of_peak(flops: float, ms: float) -> float:
+    return flops / (ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS
+
+
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "render_traffic.json")
-KERNEL_SOURCES = ("paper_2305_07450_amd/csrc/trace.hpp", "paper_2305_07450_amd/csrc/render.hip")
+ADJOINT_FILE = os.path.join(ROOT, "profiles", "adjoint_fp32.json")
+CSRC = "paper_2305_07450_amd/csrc/"
+KERNEL_SOURCES = (CSRC + "trace.hpp", CSRC + "render.hip")
+ADJOINT_SOURCES = (CSRC + "trace.hpp", CSRC + "adjoint.hip")
 
 
-def kernel_digest() -> str:
+def source_digest(paths) -> str:
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
+    for p in paths:
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def measured_profile(workload: str) -> dict:
-    """Figures per launch from the committed rocprofv3 counter runs (HBM bytes,
-    executed FP32 FLOPs), or {} when the kernel source has changed since they
-    were taken."""
+def kernel_digest() -> str:
+    return source_digest(KERNEL_SOURCES)
+
+
+def measured_profile(path: str, sources, workload: str) -> dict:
+    """Figures per launch from a committed rocprofv3 counter run (HBM bytes,
+    FP32 instruction counts), or {} when the kernel source has changed since
+    they were taken."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return {}
-    if t.get("kernel_digest") != kernel_digest() or t.get("workload") != workload:
+    if t.get("kernel_digest") != source_digest(sources) or t.get("workload") != workload:
         return {}
     return t
 
 
-def cpu_baseline(wl, seconds: float):
+def frame_parity(oracle, wl, gpu_rgb, gpu_ids, threads):
+    """Parity of the headline frame against the FP64 oracle, the bar of the
+    GPU parity tests: primary ids on non-grazing pixels, colour within 1e-4
+    on the pixels the oracle classifies well conditioned, and the shares."""
+    import numpy as np
+    base = oracle.render(wl.scene, wl.camera, wl.W, wl.H, wl.depth, threads=threads)
+    ok = oracle.condition(wl.scene, wl.camera, wl.W, wl.H, wl.depth, base=base, threads=threads)
+    nongrazing = base.margin >= oracle.GRAZING
+    err = np.abs(gpu_rgb - base.rgb).max(1)
+    checked = nongrazing & ok
+    return {"pixels": int(err.size),
+            "id_mismatch_nongrazing": int(((gpu_ids != base.prim_id) & nongrazing).sum()),
+            "id_mismatch_all": int((gpu_ids != base.prim_id).sum()),
+            "grazing_share": float((~nongrazing).mean()),
+            "ill_conditioned_share": float((~ok).mean()),
+            "colour_mismatch_frac_nongrazing": float(((err > 1e-4) & nongrazing).sum()
+                                                     / max(int(nongrazing.sum()), 1)),
+            "colour_mismatch_checked": int(((err > 1e-4) & checked).sum()),
+            "max_err_checked": float(err[checked].max()) if checked.any() else 0.0,
+            "tolerance": 1e-4}
+
+
+def cpu_baseline(wl, seconds: float, gpu_rgb=None, gpu_ids=None):
     """The FP64 oracle, as it stands, on this host's cores: whole frames of
-    the same workload until `seconds` have passed (at least one)."""
+    the same workload until `seconds` have passed (at least one).  With the
+    GPU's image of that frame, also its parity statistics against the oracle
+    (returned separately; not part of the timed sample)."""
     import oracle
     oracle.build()
     threads = oracle.default_threads()
@@ -68,10 +118,14 @@ def cpu_baseline(wl, seconds: float):
         if el >= seconds:
             break
     per_frame = el / frames
-    return {"value": round(wl.W * wl.H / per_frame / 1e6, 4), "unit": "Mrays/s (primary)",
+    base = {"value": round(wl.W * wl.H / per_frame / 1e6, 4), "unit": "Mrays/s (primary)",
             "cores": threads, "kind": "oracle",
             "sample": f"{frames} whole {wl.W}x{wl.H} frame(s) of the same scene, "
                       f"{per_frame:.3f} s per frame, FP64 C oracle with OpenMP"}
+    parity = None
+    if gpu_rgb is not None:
+        parity = frame_parity(oracle, wl, gpu_rgb, gpu_ids, threads)
+    return base, parity
 
 
 def time_gpu(fn, steps, warmup, stream):
@@ -90,6 +144,55 @@ def time_gpu(fn, steps, warmup, stream):
     return e0.elapsed_time(e1) / steps
 
 
+def time_split(prep, kern, steps, warmup, stream):
+    """Per-call HIP-event times of kern() alone and of prep() + kern() (one
+    step), on `stream`, over `steps` calls after `warmup`; and the host wall
+    clock of the whole loop.  Returns (kernel ms list, step ms list, wall ms)."""
+    import torch
+    for _ in range(warmup):
+        prep()
+        kern()
+    torch.cuda.synchronize()
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    es = [ev() for _ in range(steps + 1)]
+    ks = [ev() for _ in range(steps)]
+    ke = [ev() for _ in range(steps)]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        es[k].record(stream)
+        prep()
+        ks[k].record(stream)
+        kern()
+        ke[k].record(stream)
+    es[steps].record(stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3
+    kernel = [ks[k].elapsed_time(ke[k]) for k in range(steps)]
+    step = [es[k].elapsed_time(es[k + 1]) for k in range(steps)]
+    return kernel, step, wall
+
+
+def dist(ms):
+    """Mean, median, the paper's mean of 10 consecutive frames (the first ten
+    timed), min and max of per-frame times (ms)."""
+    import statistics
+    return {"mean": round(statistics.fmean(ms), 5), "median": round(statistics.median(ms), 5),
+            "mean_of_10": round(statistics.fmean(ms[:10]), 5),
+            "min": round(min(ms), 5), "max": round(max(ms), 5)}
+
+
+def work_rates(counts, ms):
+    """Tests per second and the fraction of the FP32 peak from the exact tests
+    the kernel executed (and the method's algorithmic count per second)."""
+    ex = test_flops(counts, True)
+    return {"tests_per_s": float("%.4g" % ((counts["sphere_tests"] + counts["plane_tests"])
+                                           / (ms * 1e-3))),
+            "executed_tests_per_s": float("%.4g" % ((counts["exec_sphere_tests"]
+                                                     + counts["exec_plane_tests"]) / (ms * 1e-3))),
+            "executed_tflops": round(ex / (ms * 1e-3) / 1e12, 3),
+            "executed_frac": round(frac_of_peak(ex, ms), 4)}
+
+
 def bench_fwd_bwd(rt, scenegen, stream, steps):
     """Differentiable workload (1280x720, 128 spheres, 1 light, depth 3):
     forward render with records + adjoint, and with re-traced decisions."""
@@ -105,6 +208,7 @@ def bench_fwd_bwd(rt, scenegen, stream, steps):
         ("albedo", (N, 3)), ("refl", (N,)), ("center", (N, 3)), ("light_pos", (L, 3)),
         ("light_int", (L,)))}
     rec = rt.Records(W, H, D)
+    counts = rt.render_counts(h.handle, wl.camera, W, H, D)
     t_fwd = time_gpu(lambda: rt.rt_render(h.handle, wl.camera, W, H, D, rgb, None, rec, stream),
                      steps, 5, stream)
     t_bwd = time_gpu(lambda: rt.rt_render_backward(h.handle, wl.camera, W, H, D, grad, g, rec,
@@ -115,13 +219,26 @@ def bench_fwd_bwd(rt, scenegen, stream, steps):
                                                 stream), steps, 5, stream)
     h.close()
     P = W * H
+    segs = counts["primary_rays"] + counts["reflection_rays"]
+    adj = measured_profile(ADJOINT_FILE, ADJOINT_SOURCES, wl.name)
+    bwd_fp32 = None
+    if adj.get("executed_fp32_flops_per_launch"):
+        f = adj["executed_fp32_flops_per_launch"]
+        bwd_fp32 = {"executed_tflops": round(f / (t_bwd * 1e-3) / 1e12, 3),
+                    "executed_frac": round(frac_of_peak(f, t_bwd), 4),
+                    "source": "FP32 VALU instruction counts x lane utilisation of the adjoint "
+                              "kernel, from rocprofv3 (profiles/adjoint_fp32.json)"}
     return {"workload": wl.name,
             "fwd_ms": round(t_fwd, 4), "bwd_ms": round(t_bwd, 4),
             "fwd_bwd_mrays_per_s_checkpoint": round(P / ((t_fwd + t_bwd) * 1e-3) / 1e6, 2),
             "bwd_recompute_ms": round(t_bwd_re, 4),
             "fwd_bwd_mrays_per_s_recompute": round(P / ((t_fwd_plain + t_bwd_re) * 1e-3) / 1e6,
                                                    2),
-            "fwd_only_mrays_per_s": round(P / (t_fwd_plain * 1e-3) / 1e6, 2)}
+            "fwd_only_mrays_per_s": round(P / (t_fwd_plain * 1e-3) / 1e6, 2),
+            "fwd_work": work_rates(counts, t_fwd_plain),
+            "bwd_segments_per_s": float("%.4g" % (segs / (t_bwd * 1e-3))),
+            "bwd_fp32": bwd_fp32,
+            "work_per_frame": counts}
 
 
 def bench_batch(rt, scenegen, stream, steps):
@@ -136,6 +253,7 @@ def bench_batch(rt, scenegen, stream, steps):
                            [w.W for w in wls], [w.H for w in wls], [w.depth for w in wls], outs,
                            autotune=True, stream=stream)
     create_s = time.perf_counter() - t0
+    counts = rt.batch_counts(b)
     t_graph = time_gpu(lambda: rt.rt_batch_launch(b, stream), steps, 3, stream)
 
     def sequential():
@@ -153,20 +271,23 @@ def bench_batch(rt, scenegen, stream, steps):
     for h in handles:
         h.close()
     P = sum(w.W * w.H for w in wls)
+    rays = counts["primary_rays"] + counts["reflection_rays"] + counts["shadow_rays"]
     return {"workload": "batch_64scenes", "scenes": len(wls), "pixels": P,
             "graph_ms": round(t_graph, 4), "sequential_ms_gpu": round(t_seq, 4),
             "sequential_ms_wall": round(t_seq_wall, 4),
             "batched_mrays_per_s": round(P / (t_graph * 1e-3) / 1e6, 2),
+            "batched_total_mrays_per_s": round(rays / (t_graph * 1e-3) / 1e6, 2),
             "sequential_mrays_per_s": round(P / (max(t_seq, t_seq_wall) * 1e-3) / 1e6, 2),
             "speedup": round(max(t_seq, t_seq_wall) / t_graph, 3),
             "shape": {"workgroups": shape[0], "tile_w": shape[1], "tile_h": shape[2]},
-            "create_s": round(create_s, 3)}
+            "create_s": round(create_s, 3),
+            "work": work_rates(counts, t_graph), "work_per_launch": counts}
 
 
 def bench_configs(rt, scenegen, stream, indices=(0, 2), reps=20):
     """The other single-image workloads (the small 256x144 scene and 4K with 512
-    spheres): frame time, frames/s, primary Mrays/s and the brute-force
-    equivalent FP32 rate, measured like the headline."""
+    spheres): frame time, frames/s, primary Mrays/s, tests per second and the
+    fraction of the FP32 peak from the exact tests the kernel executes."""
     out = {}
     for i in indices:
         wl = scenegen.make_workload(i)
@@ -176,13 +297,9 @@ def bench_configs(rt, scenegen, stream, indices=(0, 2), reps=20):
         counts = rt.render_counts(h.handle, wl.camera, W, H, D)
         ms = time_gpu(lambda: rt.rt_render(h.handle, wl.camera, W, H, D, rgb, None, None, stream),
                       reps, 3, stream)
-        flops = FLOP_SPHERE_TEST * counts["sphere_tests"] + FLOP_PLANE_TEST * counts["plane_tests"]
-        # the brute-force count over time: with the bounds deciding most pairs
-        # without the exact test this is an equivalent rate, and at 4K it
-        # exceeds what the chip could issue
         out[wl.name] = {"ms": round(ms, 4), "fps": round(1e3 / ms, 1),
                         "primary_mrays_per_s": round(W * H / (ms * 1e-3) / 1e6, 1),
-                        "brute_force_equivalent_tflops": round(flops / (ms * 1e-3) / 1e12, 2)}
+                        **work_rates(counts, ms)}
         h.close()
     return out
 
@@ -289,7 +406,7 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", type=int, default=1, choices=[0, 1, 2, 4])
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -322,29 +439,29 @@ def main():
     h = rt.SceneHandle(wl.scene)
     rgb = torch.empty((H, W, 3), dtype=torch.float32, device=dev)
     counts = rt.render_counts(h.handle, wl.camera, W, H, D)
+    counts_bf = rt.render_counts(h.handle, wl.camera, W, H, D, flags=rt.RT_RENDER_NO_PREFILTER)
     stream = torch.cuda.current_stream()
-    for _ in range(args.warmup):
-        rt.rt_render(h.handle, wl.camera, W, H, D, rgb, None, None, stream)
+    ready = rt.RT_RENDER_CONES_READY
+    # one step = rt_render's two launches, issued apart so that the render
+    # kernel gets events of its own: the eye cones, then the render
+    prep = lambda: rt.rt_render_prepare(h.handle, wl.camera, stream)
+    kern = lambda: rt.rt_render_ex(h.handle, wl.camera, W, H, D, rgb, None, None, ready, stream)
     torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        rt.rt_render(h.handle, wl.camera, W, H, D, rgb, None, None, stream)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_kernel = ev0.elapsed_time(ev1) / args.steps      # GPU time per launch (events)
-    ms_step = max(wall * 1e3 / args.steps, ms_kernel)
+    kernel_ms, step_ms, wall = time_split(prep, kern, args.steps, args.warmup, stream)
+    ms_step_gpu = sum(step_ms) / args.steps
+    ms_step = max(wall / args.steps, ms_step_gpu)
+    ms_kernel = sum(kernel_ms) / args.steps
     assert torch.isfinite(rgb).all()
+    ids = torch.empty((H, W), dtype=torch.int32, device=dev)
+    rt.rt_render(h.handle, wl.camera, W, H, D, rgb, ids, None, stream)
+    torch.cuda.synchronize()
+    frame_rgb = rgb.cpu().numpy().reshape(-1, 3).astype("float64")
+    frame_ids = ids.cpu().numpy().reshape(-1)
 
     rays = counts["primary_rays"] + counts["reflection_rays"] + counts["shadow_rays"]
-    flops = FLOP_SPHERE_TEST * counts["sphere_tests"] + FLOP_PLANE_TEST * counts["plane_tests"]
+    flops = test_flops(counts, True)
     achieved = flops / (ms_kernel * 1e-3) / 1e12
-    prof = measured_profile(wl.name)
-    traffic = prof.get("bytes_per_launch")
-    executed = prof.get("executed_fp32_flops_per_launch")
+    prof = measured_profile(TRAFFIC_FILE, KERNEL_SOURCES, wl.name)
     out = {
         "metric": "primary Mrays/s at 1080p (also fps, total Mrays/s, FP32 roofline fraction)",
         "value": round(W * H / (ms_step * 1e-3) / 1e6, 3),
@@ -358,29 +475,40 @@ def main():
                    "seed": scenegen.canonical_seed(args.workload), "parallelism": "single-gpu"},
         "fps": round(1e3 / ms_step, 2),
         "total_mrays_per_s": round(rays / (ms_step * 1e-3) / 1e6, 2),
-        "tests_per_s": float("%.4g" % ((counts["sphere_tests"] + counts["plane_tests"])
-                                       / (ms_step * 1e-3))),
+        "frame_ms": dist(step_ms),
+        "render_kernel_ms": dist(kernel_ms),
+        **{k: v for k, v in work_rates(counts, ms_step).items()
+           if k in ("tests_per_s", "executed_tests_per_s")},
         "work_per_frame": counts,
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                     "traffic": traffic,
-                     "frac_of_nonpacked_peak": round(achieved / PEAK_FP32_NONPACKED, 4),
-                     # FP32 arithmetic the kernel issued (rocprofv3 VALU counts x lane
-                     # utilisation), beside the brute-force count above
-                     "executed_tflops": (round(executed / (ms_kernel * 1e-3) / 1e12, 3)
-                                         if executed else None),
+                     "traffic": prof.get("bytes_per_launch"),
+                     "kernel": "render_kernel (culled: cone tests and wave bounds)",
                      "kernel_ms": round(ms_kernel, 5),
-                     "flops_per_launch": flops},
+                     "flops_per_launch": flops,
+                     "counted": "exact ray-sphere tests x 16 FLOP + ray-plane tests x 12 FLOP "
+                                "that the kernel executes, once per ray whose result can still "
+                                "matter (rt_render_counts [5], [6])"},
     }
     if not args.no_extras:
-        # the same image through the kernel variants kept for comparison
-        variants = {}
-        for name, flags in (("no_prefilter", rt.RT_RENDER_NO_PREFILTER),):
-            ms = time_gpu(lambda: rt.rt_render_ex(h.handle, wl.camera, W, H, D, rgb, None, None,
-                                                  flags, stream), 20, 3, stream)
-            variants[name] = {"ms": round(ms, 4),
-                              "tflops_algorithmic": round(flops / (ms * 1e-3) / 1e12, 2)}
-        out["variants"] = variants
+        # the method's brute force: the same image without the culling, whose
+        # executed tests are exactly the method's algorithmic count
+        flags = rt.RT_RENDER_NO_PREFILTER | ready
+        bf_kernel, bf_step, _ = time_split(
+            prep, lambda: rt.rt_render_ex(h.handle, wl.camera, W, H, D, rgb, None, None, flags,
+                                          stream), 20, 3, stream)
+        ms_bf = sum(bf_kernel) / len(bf_kernel)
+        bf_flops = test_flops(counts_bf, True)
+        out["brute_force"] = {
+            "kernel": "render_kernel without cone tests and wave bounds (RT_RENDER_NO_PREFILTER)",
+            "kernel_ms": round(ms_bf, 5), "step_ms": round(sum(bf_step) / len(bf_step), 5),
+            "flops_per_launch": bf_flops,
+            "achieved": round(bf_flops / (ms_bf * 1e-3) / 1e12, 3),
+            "frac": round(frac_of_peak(bf_flops, ms_bf), 4),
+            "executed_equals_algorithmic": (counts_bf["exec_sphere_tests"]
+                                            == counts_bf["sphere_tests"]
+                                            and counts_bf["exec_plane_tests"]
+                                            == counts_bf["plane_tests"])}
     h.close()
     if not args.no_extras:
         out["fwd_bwd"] = bench_fwd_bwd(rt, scenegen, stream, 20)
@@ -390,7 +518,8 @@ def main():
         out["interactive"] = bench_interactive(rt, scenegen, stream)
         out["paper_context"] = PAPER_CONTEXT
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+        out["cpu_baseline"], out["parity"] = cpu_baseline(wl, args.cpu_seconds, frame_rgb,
+                                                          frame_ids)
     print(json.dumps(out), flush=True)
 
 

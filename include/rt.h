@@ -161,6 +161,11 @@ rt_status rt_scene_set_sky(rt_scene scene, const float* rgb, int32_t w, int32_t 
 
 rt_status rt_scene_destroy(rt_scene scene);
 
+/* Counts of an uploaded scene (any pointer may be NULL), so that a binding
+ * can size gradient buffers and check the caller's: host-only, no HIP call. */
+rt_status rt_scene_counts(rt_scene scene, int32_t* n_spheres, int32_t* n_planes,
+                          int32_t* n_lights);
+
 /* Bytes of records for a W x H image at the given depth. */
 int64_t rt_records_bytes(int32_t W, int32_t H, int32_t depth);
 
@@ -170,7 +175,13 @@ int64_t rt_records_bytes(int32_t W, int32_t H, int32_t depth);
  *   rgb_out  device float32 [H][W][3], linear colour, not clamped;
  *   id_out   device int32 [H][W] primary hit id (-1 = miss), or NULL;
  *   rec      records for rt_render_backward, or NULL.
- * Launches one kernel; no allocation, capture-safe. */
+ * Launches two kernels: the cones of the spheres seen from the camera's eye,
+ * written into the scene's own buffer, then the render.  No allocation,
+ * capture-safe.  Because the eye-cone table lives in the scene, calls that
+ * write it (rt_render, rt_render_ex, rt_render_soft, rt_render_counts and
+ * rt_render_backward with rec == NULL) must not overlap in time for one
+ * scene: on one stream they are ordered; on different streams the caller
+ * orders them (events), or a render may read another call's cones. */
 rt_status rt_render(rt_scene scene, const rt_camera* cam, int32_t W, int32_t H, int32_t depth,
                     float* rgb_out, int32_t* id_out, const rt_records* rec, void* stream);
 
@@ -183,10 +194,29 @@ rt_status rt_render(rt_scene scene, const rt_camera* cam, int32_t W, int32_t H, 
                                       either way; this flag exists to check
                                       that */
 
-/* rt_render with flags (0 = rt_render). */
+#define RT_RENDER_CONES_READY 2u   /* rt_render_ex only: skip the eye-cone
+                                      launch; the caller has called
+                                      rt_render_prepare with a camera at the
+                                      same eye position, on the same stream,
+                                      after the last call that rewrote the
+                                      scene's cones (any render, count or
+                                      re-traced backward of the scene, or a
+                                      scene update).  Stale cones give a wrong
+                                      image, never an out-of-bounds access */
+
+/* rt_render with flags (0 = rt_render); the same two launches (one with
+ * RT_RENDER_CONES_READY) and the same rule for calls on one scene. */
 rt_status rt_render_ex(rt_scene scene, const rt_camera* cam, int32_t W, int32_t H, int32_t depth,
                        float* rgb_out, int32_t* id_out, const rt_records* rec, uint32_t flags,
                        void* stream);
+
+/* The first of rt_render's two launches on its own: the cones of the scene's
+ * spheres seen from the camera's eye, written into the scene's buffer, for a
+ * following rt_render_ex with RT_RENDER_CONES_READY (so that the render
+ * kernel can be timed or captured on its own).  Only the eye position and
+ * the camera's validity matter.  One launch, no allocation, capture-safe; the
+ * same overlap rule as rt_render. */
+rt_status rt_render_prepare(rt_scene scene, const rt_camera* cam, void* stream);
 
 /* Render one image with soft shadows (the paper's soft cast shadows, Section
  * 3.6.1): every light is a sphere of radius light_radius about its position,
@@ -210,14 +240,24 @@ rt_status rt_render_soft(rt_scene scene, const rt_camera* cam, int32_t W, int32_
                          int32_t depth, int32_t samples, float light_radius, float* rgb_out,
                          int32_t* id_out, uint32_t flags, void* stream);
 
-/* Work counters of the render of one image, as the method defines its work
- * (Sections 3.4.1 and 3.6: every segment tests every primitive; a shadow ray
- * is traced only when n.L > 0 and tests primitives in ascending id order up
- * to its first occluder).  Adds to counts (device int64 [5], caller zeroes):
- * [0] ray-sphere tests, [1] ray-plane tests, [2] primary rays,
- * [3] reflection rays, [4] shadow rays.  Renders no image; one launch. */
+/* Work counters of the render of one image.  Adds to counts (device int64
+ * [RT_NUM_COUNTS], caller zeroes):
+ *   [0] ray-sphere tests and [1] ray-plane tests as the method defines its
+ *       work (Sections 3.4.1 and 3.6: every segment tests every primitive; a
+ *       shadow ray is traced only when n.L > 0 and tests primitives in
+ *       ascending id order up to its first occluder);
+ *   [2] primary rays, [3] reflection rays, [4] shadow rays;
+ *   [5] ray-sphere tests and [6] ray-plane tests the render kernel actually
+ *       executes, once per ray whose result can still matter: pairs that the
+ *       cone tests and wave bounds decide without the exact test are not
+ *       counted.  With flags = RT_RENDER_NO_PREFILTER the counts are those of
+ *       the kernel without them, whose executed tests equal [0] and [1].
+ * Renders no image.  Launches the eye-cone kernel and the counting kernel (the
+ * render's path code with per-lane counters), so it must not overlap other
+ * renders of the same scene (see rt_render). */
+#define RT_NUM_COUNTS 7
 rt_status rt_render_counts(rt_scene scene, const rt_camera* cam, int32_t W, int32_t H,
-                           int32_t depth, int64_t* counts, void* stream);
+                           int32_t depth, int64_t* counts, uint32_t flags, void* stream);
 
 /* Adjoint of rt_render with every discrete decision fixed (hit primitive per
  * segment, lit lights, path length): given dLoss/dRGB (device float32
@@ -229,9 +269,17 @@ rt_status rt_render_counts(rt_scene scene, const rt_camera* cam, int32_t W, int3
  * rt_render for the same scene, camera, size and depth.  The sum over pixels
  * is deterministic (fixed order, no floating-point atomics).  With a skybox,
  * a path that ends in a miss also feeds its last mirror direction through
- * the UV mapping and the bilinear weights (texels are constants).  Scenes of
- * more than 2335 spheres (the per-wave gradient accumulators must fit in
- * LDS) return RT_ERR_UNSUPPORTED.  No allocation; capture-safe. */
+ * the UV mapping and the bilinear weights (texels are constants).  The
+ * per-wave gradient accumulators (7 N + 4 L + 4 floats) live in LDS: up to
+ * 2335 spheres within 64 KiB per workgroup (four waves each for small
+ * scenes), beyond that one wave per workgroup with up to the device's LDS
+ * per workgroup (160 KiB on gfx950: every scene up to RT_MAX_SPHERES); a
+ * scene that does not fit returns RT_ERR_UNSUPPORTED and writes nothing.
+ * No allocation; capture-safe.  With
+ * rec == NULL the re-trace first rewrites the scene's eye-cone table, so it
+ * must not overlap other renders of the same scene (see rt_render); the
+ * per-workgroup gradient partials also live in the scene's buffer, so two
+ * backward calls of one scene must not overlap either. */
 rt_status rt_render_backward(rt_scene scene, const rt_camera* cam, int32_t W, int32_t H,
                              int32_t depth, const float* grad_rgb, const rt_records* rec,
                              const rt_grads* grads, void* stream);
@@ -263,6 +311,14 @@ rt_status rt_batch_launch(rt_batch batch, void* stream);
 /* The same launch without the graph (a plain kernel launch), with the same
  * skybox check. */
 rt_status rt_batch_launch_direct(rt_batch batch, void* stream);
+
+/* Work counters of one batch launch, as rt_render_counts gives them for a
+ * single image (RT_NUM_COUNTS int64 added to counts, device memory, caller
+ * zeroes): the batch kernel with its chosen launch shape, plus per-lane
+ * counters, launched directly (no graph).  The algorithmic counts [0..4] are
+ * the sum of the single renders'; the executed tests [5], [6] depend on how
+ * the launch shape groups pixels into waves.  Renders the images as well. */
+rt_status rt_batch_counts(rt_batch batch, int64_t* counts, void* stream);
 
 /* Launch shape chosen for the batch: workgroups and pixel-tile width and
  * height (any pointer may be NULL). */

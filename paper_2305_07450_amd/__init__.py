@@ -27,11 +27,13 @@ RT_MAX_LIGHTS = 8
 RT_MAX_SPHERES = 4096
 RT_MAX_PLANES = 16
 RT_RENDER_NO_PREFILTER = 1
+RT_RENDER_CONES_READY = 2
 RT_MAX_SAMPLES = 4096
 RT_MAX_SKY_DIM = 16384
 RT_MAX_DIM = 16384
 RT_MAX_BATCH = 4096
 RT_FRAME_RGB32F, RT_FRAME_ARGB8 = 0, 1
+RT_NUM_COUNTS = 7
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(
@@ -88,14 +90,17 @@ _sig = {
     "rt_scene_update": (C.c_int, [_vp, C.POINTER(rt_scene_desc), _vp]),
     "rt_scene_set_sky": (C.c_int, [_vp, _vp, _i32, _i32, C.c_int, _vp]),
     "rt_scene_destroy": (C.c_int, [_vp]),
+    "rt_scene_counts": (C.c_int, [_vp, C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_i32)]),
     "rt_records_bytes": (C.c_int64, [_i32, _i32, _i32]),
     "rt_render": (C.c_int, [_vp, C.POINTER(rt_camera), _i32, _i32, _i32, _vp, _vp,
                             C.POINTER(rt_records), _vp]),
     "rt_render_ex": (C.c_int, [_vp, C.POINTER(rt_camera), _i32, _i32, _i32, _vp, _vp,
                                C.POINTER(rt_records), C.c_uint32, _vp]),
+    "rt_render_prepare": (C.c_int, [_vp, C.POINTER(rt_camera), _vp]),
     "rt_render_soft": (C.c_int, [_vp, C.POINTER(rt_camera), _i32, _i32, _i32, _i32, C.c_float,
                                  _vp, _vp, C.c_uint32, _vp]),
-    "rt_render_counts": (C.c_int, [_vp, C.POINTER(rt_camera), _i32, _i32, _i32, _vp, _vp]),
+    "rt_render_counts": (C.c_int, [_vp, C.POINTER(rt_camera), _i32, _i32, _i32, _vp, C.c_uint32,
+                                   _vp]),
     "rt_render_backward": (C.c_int, [_vp, C.POINTER(rt_camera), _i32, _i32, _i32, _vp,
                                      C.POINTER(rt_records), C.POINTER(rt_grads), _vp]),
     "rt_batch_create": (C.c_int, [_i32, C.POINTER(_vp), C.POINTER(rt_camera), C.POINTER(_i32),
@@ -104,6 +109,7 @@ _sig = {
     "rt_batch_launch": (C.c_int, [_vp, _vp]),
     "rt_batch_launch_direct": (C.c_int, [_vp, _vp]),
     "rt_batch_shape": (C.c_int, [_vp, C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_i32)]),
+    "rt_batch_counts": (C.c_int, [_vp, _vp, _vp]),
     "rt_batch_destroy": (C.c_int, [_vp]),
     "rt_frame_create": (C.c_int, [_vp, C.POINTER(rt_frame_desc), C.POINTER(_vp)]),
     "rt_frame_submit": (C.c_int, [_vp, C.POINTER(rt_frame_input), _vp]),
@@ -152,6 +158,49 @@ def _ptr(t) -> Optional[int]:
     return t.ctypes.data if t.size else None
 
 
+def _dev(t, name: str, dtype: torch.dtype, numel: int, optional: bool = False) -> Optional[int]:
+    """Device pointer of a caller-owned buffer, after checking on the host that
+    it is a contiguous CUDA tensor of `dtype` holding at least `numel`
+    elements: the C side cannot see buffer sizes, so an undersized or
+    mistyped buffer would become an out-of-bounds device access.  Raises
+    ValueError before any call into the library."""
+    if t is None:
+        if optional:
+            return None
+        raise ValueError(f"{name} is required")
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name} must be a torch tensor, not {type(t).__name__}")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device (CUDA) tensor, not on {t.device}")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, not {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() < max(int(numel), 0):
+        raise ValueError(f"{name} holds {t.numel()} elements, {int(numel)} needed")
+    return t.data_ptr() if t.numel() else None
+
+
+def _records_arg(rec, W: int, H: int, depth: int):
+    """rt_records of a Records object after checking it covers W x H x (depth+1)."""
+    if rec is None:
+        return None
+    if not isinstance(rec, Records):
+        raise ValueError("rec must be a Records object")
+    _dev(rec.buf, "records", torch.uint8, 0)
+    need = (int(depth) + 1) * int(W) * int(H)
+    if rec.n < need:
+        raise ValueError(f"records hold {rec.n} pixel-segments, {need} needed")
+    return C.byref(rec.c)
+
+
+def rt_scene_counts(handle: int):
+    """(n_spheres, n_planes, n_lights) of an uploaded scene."""
+    n, p, l = _i32(), _i32(), _i32()
+    _check(_lib.rt_scene_counts(handle, C.byref(n), C.byref(p), C.byref(l)))
+    return n.value, p.value, l.value
+
+
 def make_camera(cam) -> rt_camera:
     """rt_camera from any object with eye, yaw_deg, pitch_deg, fov_deg."""
     return rt_camera((C.c_float * 3)(*[float(v) for v in cam.eye]), float(cam.yaw_deg),
@@ -179,6 +228,12 @@ class _Desc:
         n_sph = int(vals[0].shape[0]) if vals[0].ndim else 0
         n_pl = int(vals[3].shape[0]) if vals[3].ndim else 0
         n_l = int(vals[6].shape[0]) if vals[6].ndim else 0
+        # the library reads exactly these many floats from each array
+        for name, v, want in zip(names, vals, (4 * n_sph, 4 * n_sph, n_sph, 4 * n_pl, 4 * n_pl,
+                                                n_pl, 4 * n_l)):
+            got = int(v.numel() if isinstance(v, torch.Tensor) else v.size)
+            if got != want:
+                raise ValueError(f"scene array {name} has {got} values, {want} expected")
         self.c = rt_scene_desc(
             n_sph, n_pl, n_l, int(scene.spec_model),
             *[_ptr(v) for v in vals],
@@ -235,30 +290,48 @@ class Records:
 
     def __init__(self, W: int, H: int, depth: int, device="cuda"):
         n = (depth + 1) * H * W
+        self.n = n
         self.buf = torch.empty(rt_records_bytes(W, H, depth), dtype=torch.uint8, device=device)
         self.ids = self.buf[:4 * n].view(torch.int32).view(depth + 1, H, W)
         self.lit = self.buf[4 * n:].view(depth + 1, H, W)
         self.c = rt_records(self.ids.data_ptr(), self.lit.data_ptr(), self.buf.numel())
 
 
+def _image_args(W: int, H: int, rgb_out, id_out):
+    P = int(W) * int(H)
+    return (_dev(rgb_out, "rgb_out", torch.float32, 3 * P),
+            _dev(id_out, "id_out", torch.int32, P, optional=True))
+
+
 def rt_render(handle: int, camera, W: int, H: int, depth: int, rgb_out: torch.Tensor,
               id_out: Optional[torch.Tensor] = None, rec: Optional[Records] = None,
               stream=None):
     cam = make_camera(camera)
-    _check(_lib.rt_render(handle, C.byref(cam), W, H, depth, _ptr(rgb_out), _ptr(id_out),
-                          C.byref(rec.c) if rec is not None else None, _stream(stream)))
+    rgb_p, id_p = _image_args(W, H, rgb_out, id_out)
+    rec_p = _records_arg(rec, W, H, depth)
+    _check(_lib.rt_render(handle, C.byref(cam), W, H, depth, rgb_p, id_p, rec_p,
+                          _stream(stream)))
 
 
 def rt_render_ex(handle: int, camera, W: int, H: int, depth: int, rgb_out: torch.Tensor,
                  id_out: Optional[torch.Tensor] = None, rec: Optional["Records"] = None,
                  flags: int = 0, stream=None):
     cam = make_camera(camera)
-    _check(_lib.rt_render_ex(handle, C.byref(cam), W, H, depth, _ptr(rgb_out), _ptr(id_out),
-                             C.byref(rec.c) if rec is not None else None, int(flags),
+    rgb_p, id_p = _image_args(W, H, rgb_out, id_out)
+    rec_p = _records_arg(rec, W, H, depth)
+    _check(_lib.rt_render_ex(handle, C.byref(cam), W, H, depth, rgb_p, id_p, rec_p, int(flags),
                              _stream(stream)))
 
 
-COUNT_NAMES = ("sphere_tests", "plane_tests", "primary_rays", "reflection_rays", "shadow_rays")
+# algorithmic tests, rays, then the tests the kernel executes (include/rt.h)
+def rt_render_prepare(handle: int, camera, stream=None):
+    """The eye-cone launch of rt_render on its own (see RT_RENDER_CONES_READY)."""
+    cam = make_camera(camera)
+    _check(_lib.rt_render_prepare(handle, C.byref(cam), _stream(stream)))
+
+
+COUNT_NAMES = ("sphere_tests", "plane_tests", "primary_rays", "reflection_rays", "shadow_rays",
+               "exec_sphere_tests", "exec_plane_tests")
 
 
 def rt_render_soft(handle: int, camera, W: int, H: int, depth: int, samples: int,
@@ -267,22 +340,25 @@ def rt_render_soft(handle: int, camera, W: int, H: int, depth: int, samples: int
     """Soft shadows: every light a sphere of radius light_radius sampled at
     `samples` points (see include/rt.h)."""
     cam = make_camera(camera)
+    rgb_p, id_p = _image_args(W, H, rgb_out, id_out)
     _check(_lib.rt_render_soft(handle, C.byref(cam), W, H, depth, int(samples),
-                               float(light_radius), _ptr(rgb_out), _ptr(id_out), int(flags),
-                               _stream(stream)))
+                               float(light_radius), rgb_p, id_p, int(flags), _stream(stream)))
 
 
 def rt_render_counts(handle: int, camera, W: int, H: int, depth: int, counts: torch.Tensor,
-                     stream=None):
-    """Add the algorithmic work counters of one render to counts (int64 [5])."""
+                     flags: int = 0, stream=None):
+    """Add the work counters of one render to counts (int64 [RT_NUM_COUNTS]);
+    flags = RT_RENDER_NO_PREFILTER counts the kernel without the culling."""
     cam = make_camera(camera)
-    _check(_lib.rt_render_counts(handle, C.byref(cam), W, H, depth, _ptr(counts),
+    cnt_p = _dev(counts, "counts", torch.int64, RT_NUM_COUNTS)
+    _check(_lib.rt_render_counts(handle, C.byref(cam), W, H, depth, cnt_p, int(flags),
                                  _stream(stream)))
 
 
-def render_counts(handle: int, camera, W: int, H: int, depth: int) -> Dict[str, int]:
-    c = torch.zeros(5, dtype=torch.int64, device="cuda")
-    rt_render_counts(handle, camera, W, H, depth, c)
+def render_counts(handle: int, camera, W: int, H: int, depth: int,
+                  flags: int = 0) -> Dict[str, int]:
+    c = torch.zeros(RT_NUM_COUNTS, dtype=torch.int64, device="cuda")
+    rt_render_counts(handle, camera, W, H, depth, c, flags)
     return dict(zip(COUNT_NAMES, c.cpu().tolist()))
 
 
@@ -290,20 +366,38 @@ def rt_render_backward(handle: int, camera, W: int, H: int, depth: int, grad_rgb
                        grads: Dict[str, torch.Tensor], rec: Optional[Records] = None,
                        stream=None):
     cam = make_camera(camera)
-    g = rt_grads(*[_ptr(grads.get(k)) for k in
-                   ("albedo", "refl", "center", "light_pos", "light_int")])
-    _check(_lib.rt_render_backward(handle, C.byref(cam), W, H, depth, _ptr(grad_rgb),
-                                   C.byref(rec.c) if rec is not None else None, C.byref(g),
+    grad_p = _dev(grad_rgb, "grad_rgb", torch.float32, 3 * int(W) * int(H))
+    rec_p = _records_arg(rec, W, H, depth)
+    g = _grads_arg(handle, grads)
+    _check(_lib.rt_render_backward(handle, C.byref(cam), W, H, depth, grad_p, rec_p, C.byref(g),
                                    _stream(stream)))
+
+
+GRAD_NAMES = ("albedo", "refl", "center", "light_pos", "light_int")
+
+
+def _grads_arg(handle: int, grads: Dict[str, torch.Tensor]) -> rt_grads:
+    """rt_grads from a dict of device float32 tensors (missing or None entries
+    are skipped), each checked against the scene's counts."""
+    unknown = set(grads) - set(GRAD_NAMES)
+    if unknown:
+        raise ValueError(f"unknown gradient groups {sorted(unknown)}")
+    N, _, L = rt_scene_counts(handle)
+    sizes = dict(albedo=3 * N, refl=N, center=3 * N, light_pos=3 * L, light_int=L)
+    return rt_grads(*[_dev(grads.get(k), f"grads[{k!r}]", torch.float32, sizes[k],
+                           optional=True) for k in GRAD_NAMES])
 
 
 def rt_batch_create(handles: Sequence[int], cameras, W: Sequence[int], H: Sequence[int],
                     depth: Sequence[int], rgb_outs: Sequence[torch.Tensor], autotune: bool = True,
                     stream=None) -> int:
     n = len(handles)
+    if not (len(cameras) == len(W) == len(H) == len(depth) == len(rgb_outs) == n):
+        raise ValueError("batch arrays differ in length")
     cams = (rt_camera * n)(*[make_camera(c) for c in cameras])
     arr = lambda v: (_i32 * n)(*[int(x) for x in v])
-    outs = (_vp * n)(*[_ptr(t) for t in rgb_outs])
+    outs = (_vp * n)(*[_dev(t, f"rgb_outs[{i}]", torch.float32, 3 * int(w) * int(h))
+                       for i, (t, w, h) in enumerate(zip(rgb_outs, W, H))])
     hs = (_vp * n)(*handles)
     b = _vp()
     _check(_lib.rt_batch_create(n, hs, cams, arr(W), arr(H), arr(depth), outs, int(autotune),
@@ -317,6 +411,19 @@ def rt_batch_launch(batch: int, stream=None):
 
 def rt_batch_launch_direct(batch: int, stream=None):
     _check(_lib.rt_batch_launch_direct(batch, _stream(stream)))
+
+
+def rt_batch_counts(batch: int, counts: torch.Tensor, stream=None):
+    """Add the work counters of one (direct) batch launch to counts (int64
+    [RT_NUM_COUNTS])."""
+    _check(_lib.rt_batch_counts(batch, _dev(counts, "counts", torch.int64, RT_NUM_COUNTS),
+                                _stream(stream)))
+
+
+def batch_counts(batch: int) -> Dict[str, int]:
+    c = torch.zeros(RT_NUM_COUNTS, dtype=torch.int64, device="cuda")
+    rt_batch_counts(batch, c)
+    return dict(zip(COUNT_NAMES, c.cpu().tolist()))
 
 
 def rt_batch_shape(batch: int):
@@ -335,10 +442,15 @@ def rt_frame_create(handle: int, W: int, H: int, rgb_out: torch.Tensor, soft: bo
     include/rt.h); rgb_out is the device image every frame renders into, fmt
     the streamed-out format (RT_FRAME_RGB32F or RT_FRAME_ARGB8)."""
     d = rt_frame_desc(int(W), int(H), int(bool(soft)), int(bool(stream_out)), int(fmt),
-                      int(flags), _ptr(rgb_out))
+                      int(flags), _dev(rgb_out, "rgb_out", torch.float32, 3 * int(W) * int(H)))
     f = _vp()
     _check(_lib.rt_frame_create(handle, C.byref(d), C.byref(f)))
+    _frame_spheres[f.value] = rt_scene_counts(handle)[0]
     return f.value
+
+
+# spheres of each frame object's scene, to check the centres of every submit
+_frame_spheres: Dict[int, int] = {}
 
 
 def rt_frame_submit(frame: int, camera, depth: int, samples: int = 1, light_radius: float = 0.0,
@@ -348,6 +460,9 @@ def rt_frame_submit(frame: int, camera, depth: int, samples: int = 1, light_radi
     pos = None
     if sphere_pos is not None:
         pos = np.ascontiguousarray(sphere_pos, dtype=np.float32)
+        want = 3 * _frame_spheres.get(frame, pos.size // 3)
+        if pos.size != want:
+            raise ValueError(f"sphere_pos has {pos.size} values, {want} expected")
     inp = rt_frame_input(make_camera(camera), int(depth), int(samples), float(light_radius),
                          _ptr(pos) if pos is not None else None)
     _check(_lib.rt_frame_submit(frame, C.byref(inp), _stream(stream)))
@@ -368,6 +483,7 @@ def rt_frame_result(frame: int, W: int = 0, H: int = 0, fmt: int = 0):
 
 
 def rt_frame_destroy(frame: int):
+    _frame_spheres.pop(frame, None)
     _check(_lib.rt_frame_destroy(frame))
 
 

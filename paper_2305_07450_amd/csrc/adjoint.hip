@@ -20,6 +20,7 @@
 // sphere id with a fixed xor butterfly and adds them into its own LDS
 // accumulator; each workgroup then writes one partial vector, and a second
 // kernel adds the partials in a fixed order.  No floating-point atomics.
+#include <mutex>
 #include <type_traits>
 
 #include "rt_internal.hpp"
@@ -28,7 +29,7 @@ namespace rtk {
 
 constexpr int kTileA = 8;
 constexpr int kBlockA = 16;        // pixels per workgroup tile edge (2 x 2 wave tiles)
-constexpr int kLdsFloats = 16384;  // 64 KiB of accumulators per workgroup
+constexpr int kLdsFloats = 16384;  // 64 KiB: accumulator budget per workgroup when it fits
 
 // Sum over the 64 lanes in a fixed order, so that runs repeat bit for bit.
 // With every lane executing: DPP adds within each row of 16 (quad swaps, half
@@ -503,19 +504,58 @@ __global__ __launch_bounds__(64 * kReduceWaves) void reduce_kernel(const float* 
 
 int adjoint_blocks(int grad_stride);
 
-bool adjoint_supported(int n_spheres) { return 7 * n_spheres + 4 * kMaxLights + 4 <= kLdsFloats; }
+// LDS a workgroup may allocate on a device, in floats (gfx950: 160 KiB),
+// queried once per device.  Scenes whose accumulators do not fit the 64 KiB
+// budget run one wave per workgroup with up to this much.
+static int lds_limit_floats(int device) {
+  static std::mutex mu;
+  static int cache[kMaxDevices];
+  if (device < 0 || device >= kMaxDevices) return kLdsFloats;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!cache[device]) {
+    int bytes = 0;
+    if (hipDeviceGetAttribute(&bytes, hipDeviceAttributeMaxSharedMemoryPerBlock, device) !=
+            hipSuccess ||
+        bytes < (int)(kLdsFloats * sizeof(float)))
+      bytes = kLdsFloats * sizeof(float);
+    cache[device] = bytes / (int)sizeof(float);
+  }
+  return cache[device];
+}
+
+// Floats of LDS a one-wave workgroup needs: 7N sphere accumulators, 4L light
+// slots and 4 spare.
+static int lds_one_wave(int n_spheres, int n_lights) { return 7 * n_spheres + 4 * n_lights + 4; }
+
+bool adjoint_supported(int n_spheres, int device) {
+  return lds_one_wave(n_spheres, kMaxLights) <= lds_limit_floats(device);
+}
+
+int adjoint_max_spheres(int device) {
+  return (lds_limit_floats(device) - lds_one_wave(0, kMaxLights)) / 7;
+}
+
+// Workgroups of the adjoint grid for an image: one per 16 x 16 tile, at most
+// adjoint_blocks() (the partial rows the scene's buffer holds).
+static int backward_blocks(const rt_scene_s& sc, const CameraDev& c, int* n_tiles_x,
+                           int* n_tiles) {
+  *n_tiles_x = (c.W + kBlockA - 1) / kBlockA;
+  *n_tiles = *n_tiles_x * ((c.H + kBlockA - 1) / kBlockA);
+  int blocks = adjoint_blocks(sc.grad_stride);
+  return blocks > *n_tiles ? *n_tiles : blocks;
+}
 
 hipError_t launch_backward(const rt_scene_s& sc, const CameraDev& c, int depth,
                            const float* grad_rgb, const int32_t* rec_ids, const uint8_t* rec_lit,
-                           const rt_grads& g, hipStream_t stream) {
+                           const rt_grads& g, float* partials, hipStream_t stream) {
   const int N = sc.n_spheres, L = sc.n_lights;
+  // up to four waves per workgroup within the 64 KiB budget; past it, one
+  // wave with all the LDS the scene needs (adjoint_supported() checked it)
   int waves = 4;
   while (waves > 1 && waves * (7 * N + 4 * L) + 4 > kLdsFloats) --waves;
   const size_t lds = (size_t)(waves * 7 * N + waves * 4 * L + 4) * sizeof(float);
-  const int n_tiles_x = (c.W + kBlockA - 1) / kBlockA;
-  const int n_tiles = n_tiles_x * ((c.H + kBlockA - 1) / kBlockA);
-  int blocks = adjoint_blocks(sc.grad_stride);
-  if (blocks > n_tiles) blocks = n_tiles;
+  int n_tiles_x, n_tiles;
+  const int blocks = backward_blocks(sc, c, &n_tiles_x, &n_tiles);
   SceneDev s = sc.view();
   // the smallest light bucket that holds the scene's lights
   // ... and depth bucket
@@ -535,14 +575,14 @@ hipError_t launch_backward(const rt_scene_s& sc, const CameraDev& c, int depth,
   };
   auto kern = rec_ids ? pick(std::true_type{}) : pick(std::false_type{});
   hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * waves), lds, stream, s, c, depth, grad_rgb,
-                     rec_ids, rec_lit, sc.partials, sc.grad_stride, n_tiles_x, n_tiles);
+                     rec_ids, rec_lit, partials, sc.grad_stride, n_tiles_x, n_tiles);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int total = 7 * N + 4 * L;
   if (total == 0) return hipSuccess;
   hipLaunchKernelGGL(reduce_kernel, dim3((total + kReduceCols - 1) / kReduceCols),
                      dim3(64 * kReduceWaves), 0, stream,
-                     (const float*)sc.partials, sc.grad_stride, blocks, N, L, g);
+                     (const float*)partials, sc.grad_stride, blocks, N, L, g);
   return hipGetLastError();
 }
 

@@ -15,6 +15,7 @@
 
 #include <algorithm>
 #include <map>
+#include <type_traits>
 #include <mutex>
 #include <new>
 #include <string>
@@ -59,23 +60,31 @@ __global__ void batch_cone_kernel(const BatchJob* __restrict__ jobs, float4* con
   }
 }
 
-template <class Bg>
+// With Cnt = Count the same launch also adds the work counters of every path
+// (trace.hpp) to counts[kNumCounts]; the render instantiation (NoCount) has
+// no counter code at all.
+template <class Bg, class Cnt>
 __global__ __launch_bounds__(256) void batch_kernel(const BatchJob* __restrict__ jobs,
                                                      const TileRef* __restrict__ queue,
                                                      int n_tiles, unsigned int* counter,
-                                                     int wave_w) {
-  __shared__ int s_tile;
+                                                     int wave_w,
+                                                     unsigned long long* __restrict__ counts) {
+  __shared__ unsigned int s_tile;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int waves = blockDim.x >> 6;
   const int wave_h = 64 / wave_w;
   const int tile_w = wave_w, tile_h = wave_h * waves;
+  Cnt cnt;
   for (;;) {
-    if (threadIdx.x == 0) s_tile = (int)atomicAdd(counter, 1u);
+    if (threadIdx.x == 0) s_tile = atomicAdd(counter, 1u);
     __syncthreads();
-    const int t = s_tile;
+    // tickets stay unsigned: each workgroup takes one past the last tile, so
+    // they reach n_tiles + grid - 1, which a signed cast could turn negative
+    // for a queue near 2^31 tiles
+    const unsigned int t = s_tile;
     __syncthreads();   // every lane has read s_tile before it is written again
-    if (t >= n_tiles) break;   // uniform: the whole workgroup leaves together
+    if (t >= (unsigned int)n_tiles) break;   // uniform: the whole workgroup leaves together
     const TileRef ref = queue[t];
     const BatchJob* jp = jobs + __builtin_amdgcn_readfirstlane(ref.job);
     // copy the descriptor word by word through the constant address space
@@ -97,15 +106,24 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchJob* __restrict__
       float cr, cg, cb;
       int prim;
       NoRecords sink;
-      trace_path<NoRecords, NoCount, true, HardShadows, Bg>(
+      trace_path<NoRecords, Cnt&, true, HardShadows, Bg>(
           job.s, primary_ray(job.c, live ? x : job.c.W - 1, live ? y : job.c.H - 1), job.depth,
-          live, cr, cg, cb, prim, sink);
+          live, cr, cg, cb, prim, sink, cnt);
       if (live) {
         const int64_t pix = (int64_t)y * job.c.W + x;
         job.rgb[3 * pix + 0] = cr;
         job.rgb[3 * pix + 1] = cg;
         job.rgb[3 * pix + 2] = cb;
       }
+    }
+  }
+  if constexpr (std::is_same<Cnt, Count>::value) {
+    // a persistent wave renders many tiles: sum its lanes in 64 bits
+    for (int j = 0; j < kNumCounts; ++j) {
+      long long v = cnt.c[j];
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+      if (lane == 0) atomicAdd(counts + j, (unsigned long long)v);
     }
   }
 }
@@ -173,7 +191,8 @@ hipError_t upload_shape(rt_batch_s* b, const Shape& sh, hipStream_t stream) {
   return e;
 }
 
-hipError_t launch_batch(rt_batch_s* b, hipStream_t stream) {
+hipError_t launch_batch(rt_batch_s* b, hipStream_t stream,
+                        unsigned long long* counts = nullptr) {
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, stream, b->counter);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -183,9 +202,12 @@ hipError_t launch_batch(rt_batch_s* b, hipStream_t stream) {
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  auto kern = b->any_sky ? batch_kernel<SkyBackground> : batch_kernel<PlainBackground>;
+  auto kern = b->any_sky ? batch_kernel<SkyBackground, NoCount>
+                         : batch_kernel<PlainBackground, NoCount>;
+  if (counts)
+    kern = b->any_sky ? batch_kernel<SkyBackground, Count> : batch_kernel<PlainBackground, Count>;
   hipLaunchKernelGGL(kern, dim3(b->shape.grid), dim3(64 * b->shape.waves), 0, stream, b->jobs,
-                     b->queue, b->n_tiles, b->counter, b->shape.wave_w);
+                     b->queue, b->n_tiles, b->counter, b->shape.wave_w, counts);
   return hipGetLastError();
 }
 
@@ -425,6 +447,15 @@ rt_status rt_batch_launch_direct(rt_batch b, void* stream) {
   rt_status st = check_skies(b);
   if (st != RT_OK) return st;
   return hip_fail(launch_batch(b, (hipStream_t)stream), "batch launch");
+}
+
+rt_status rt_batch_counts(rt_batch b, int64_t* counts, void* stream) {
+  if (!b) return err(RT_ERR_INVALID_ARG, "batch is NULL");
+  if (!counts) return err(RT_ERR_INVALID_ARG, "counts is NULL");
+  rt_status st = check_skies(b);
+  if (st != RT_OK) return st;
+  return hip_fail(launch_batch(b, (hipStream_t)stream, (unsigned long long*)counts),
+                  "batch count launch");
 }
 
 rt_status rt_batch_shape(rt_batch b, int32_t* workgroups, int32_t* tile_w, int32_t* tile_h) {

@@ -129,8 +129,13 @@ hipError_t launch_render_soft(const rt_scene_s& sc, const CameraDev& c, int dept
   return hipGetLastError();
 }
 
-// Counting launch: the same paths, plus the algorithmic counters summed per
-// wave (xor butterfly) and added to counts[kNumCounts] with integer atomics.
+// Counting launch: the same paths as render_kernel (with or without the cone
+// tests and wave bounds), plus the algorithmic and executed-test counters,
+// summed per wave (xor butterfly) and added to counts[kNumCounts] with
+// integer atomics.  The counters are per-lane adds; every branch of the path
+// code is the same as in the render, so the executed counts are those of the
+// render kernel.
+template <bool kPrefilter>
 __global__ __launch_bounds__(kRenderThreads) void count_kernel(SceneDev s, CameraDev c, int depth,
                                                     unsigned long long* __restrict__ counts) {
   const int lane = threadIdx.x;
@@ -142,8 +147,9 @@ __global__ __launch_bounds__(kRenderThreads) void count_kernel(SceneDev s, Camer
     float cr, cg, cb;
     int prim;
     NoRecords sink;
-    trace_path(s, primary_ray(c, live ? x : c.W - 1, live ? y : c.H - 1), depth, live, cr, cg,
-               cb, prim, sink, cnt);
+    trace_path<NoRecords, Count&, kPrefilter>(
+        s, primary_ray(c, live ? x : c.W - 1, live ? y : c.H - 1), depth, live, cr, cg, cb, prim,
+        sink, cnt);
   }
   for (int j = 0; j < kNumCounts; ++j) {
     int v = cnt.c[j];
@@ -154,9 +160,10 @@ __global__ __launch_bounds__(kRenderThreads) void count_kernel(SceneDev s, Camer
 }
 
 hipError_t launch_counts(const SceneDev& s, const CameraDev& c, int depth,
-                         unsigned long long* counts, hipStream_t stream) {
+                         unsigned long long* counts, bool prefilter, hipStream_t stream) {
   const dim3 grid = render_grid(c.W, c.H);
-  hipLaunchKernelGGL(count_kernel, grid, dim3(kRenderThreads), 0, stream, s, c, depth, counts);
+  auto kern = prefilter ? count_kernel<true> : count_kernel<false>;
+  hipLaunchKernelGGL(kern, grid, dim3(kRenderThreads), 0, stream, s, c, depth, counts);
   return hipGetLastError();
 }
 

@@ -346,6 +346,15 @@ rt_status rt_scene_destroy(rt_scene sc) {
   return hip_fail(e, "scene free");
 }
 
+rt_status rt_scene_counts(rt_scene sc, int32_t* n_spheres, int32_t* n_planes,
+                          int32_t* n_lights) {
+  if (!sc) return fail(RT_ERR_INVALID_ARG, "scene is NULL");
+  if (n_spheres) *n_spheres = sc->n_spheres;
+  if (n_planes) *n_planes = sc->n_planes;
+  if (n_lights) *n_lights = sc->n_lights;
+  return RT_OK;
+}
+
 int64_t rt_records_bytes(int32_t W, int32_t H, int32_t depth) {
   if (W <= 0 || H <= 0 || depth < 0 || depth > RT_MAX_DEPTH) return -1;
   return (int64_t)W * H * (depth + 1) * (int64_t)(sizeof(int32_t) + sizeof(uint8_t));
@@ -365,18 +374,28 @@ rt_status rt_render(rt_scene sc, const rt_camera* cam, int32_t W, int32_t H, int
   return rt_render_ex(sc, cam, W, H, depth, rgb_out, id_out, rec, 0, stream);
 }
 
+rt_status rt_render_prepare(rt_scene sc, const rt_camera* cam, void* stream) {
+  if (!sc) return fail(RT_ERR_INVALID_ARG, "scene is NULL");
+  // the eye cones depend on the eye position only; any valid size will do
+  rt_status st = validate_camera(cam, 1, 1, 0);
+  if (st != RT_OK) return st;
+  return hip_fail(launch_eye_cones(*sc, camera_dev(*cam, 1, 1), (hipStream_t)stream),
+                  "eye-cone launch");
+}
+
 rt_status rt_render_ex(rt_scene sc, const rt_camera* cam, int32_t W, int32_t H, int32_t depth,
                        float* rgb_out, int32_t* id_out, const rt_records* rec, uint32_t flags,
                        void* stream) {
   if (!sc) return fail(RT_ERR_INVALID_ARG, "scene is NULL");
-  if (flags & ~(uint32_t)RT_RENDER_NO_PREFILTER)
+  if (flags & ~(uint32_t)(RT_RENDER_NO_PREFILTER | RT_RENDER_CONES_READY))
     return fail(RT_ERR_INVALID_ARG, "unknown render flags 0x%x", flags);
   rt_status st = validate_camera(cam, W, H, depth);
   if (st != RT_OK) return st;
   if (!rgb_out) return fail(RT_ERR_INVALID_ARG, "rgb_out is NULL");
   if ((st = check_records(rec, W, H, depth)) != RT_OK) return st;
   CameraDev c = camera_dev(*cam, W, H);
-  hipError_t e = launch_eye_cones(*sc, c, (hipStream_t)stream);
+  hipError_t e = (flags & RT_RENDER_CONES_READY) ? hipSuccess
+                                                 : launch_eye_cones(*sc, c, (hipStream_t)stream);
   if (e == hipSuccess)
     e = launch_render(sc->view(), c, depth, rgb_out, id_out, rec ? rec->ids : nullptr,
                       rec ? rec->lit : nullptr, !(flags & RT_RENDER_NO_PREFILTER),
@@ -408,15 +427,18 @@ rt_status rt_render_soft(rt_scene sc, const rt_camera* cam, int32_t W, int32_t H
 }
 
 rt_status rt_render_counts(rt_scene sc, const rt_camera* cam, int32_t W, int32_t H,
-                           int32_t depth, int64_t* counts, void* stream) {
+                           int32_t depth, int64_t* counts, uint32_t flags, void* stream) {
   if (!sc) return fail(RT_ERR_INVALID_ARG, "scene is NULL");
+  if (flags & ~(uint32_t)RT_RENDER_NO_PREFILTER)
+    return fail(RT_ERR_INVALID_ARG, "unknown render flags 0x%x", flags);
   rt_status st = validate_camera(cam, W, H, depth);
   if (st != RT_OK) return st;
   if (!counts) return fail(RT_ERR_INVALID_ARG, "counts is NULL");
   CameraDev c = camera_dev(*cam, W, H);
   hipError_t e = launch_eye_cones(*sc, c, (hipStream_t)stream);
   if (e == hipSuccess)
-    e = launch_counts(sc->view(), c, depth, (unsigned long long*)counts, (hipStream_t)stream);
+    e = launch_counts(sc->view(), c, depth, (unsigned long long*)counts,
+                      !(flags & RT_RENDER_NO_PREFILTER), (hipStream_t)stream);
   return hip_fail(e, "count launch");
 }
 
@@ -429,14 +451,14 @@ rt_status rt_render_backward(rt_scene sc, const rt_camera* cam, int32_t W, int32
   if (!grad_rgb) return fail(RT_ERR_INVALID_ARG, "grad_rgb is NULL");
   if (!grads) return fail(RT_ERR_INVALID_ARG, "grads is NULL");
   if ((st = check_records(rec, W, H, depth)) != RT_OK) return st;
-  if (!adjoint_supported(sc->n_spheres))
-    return fail(RT_ERR_UNSUPPORTED, "rt_render_backward supports at most 2335 spheres, scene has %d",
-                sc->n_spheres);
+  if (!adjoint_supported(sc->n_spheres, sc->device))
+    return fail(RT_ERR_UNSUPPORTED, "rt_render_backward supports at most %d spheres, scene has %d",
+                adjoint_max_spheres(sc->device), sc->n_spheres);
   CameraDev c = camera_dev(*cam, W, H);
   hipError_t e = rec ? hipSuccess : launch_eye_cones(*sc, c, (hipStream_t)stream);
   if (e == hipSuccess)
     e = launch_backward(*sc, c, depth, grad_rgb, rec ? rec->ids : nullptr,
-                        rec ? rec->lit : nullptr, *grads, (hipStream_t)stream);
+                        rec ? rec->lit : nullptr, *grads, sc->partials, (hipStream_t)stream);
   return hip_fail(e, "backward launch");
 }
 

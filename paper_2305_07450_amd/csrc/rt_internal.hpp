@@ -103,12 +103,21 @@ hipError_t launch_render(const SceneDev& s, const CameraDev& c, int depth, float
                          hipStream_t stream);
 
 hipError_t launch_counts(const SceneDev& s, const CameraDev& c, int depth,
-                         unsigned long long* counts, hipStream_t stream);
+                         unsigned long long* counts, bool prefilter, hipStream_t stream);
 
-bool adjoint_supported(int n_spheres);
+// Whether the adjoint's per-wave LDS accumulators of a scene with n_spheres
+// (and up to RT_MAX_LIGHTS lights) fit a workgroup on `device`, and the
+// largest such sphere count.
+bool adjoint_supported(int n_spheres, int device);
+int adjoint_max_spheres(int device);
 
+// partials: [blocks][grad_stride] floats of device memory (the scene's own),
+// every row written before it is read.
 hipError_t launch_backward(const rt_scene_s& sc, const CameraDev& c, int depth,
                            const float* grad_rgb, const int32_t* rec_ids, const uint8_t* rec_lit,
-                           const rt_grads& g, hipStream_t stream);
+                           const rt_grads& g, float* partials, hipStream_t stream);
+
+// Device ordinals the per-device caches of the library hold.
+constexpr int kMaxDevices = 64;
 
 }  // namespace rtk

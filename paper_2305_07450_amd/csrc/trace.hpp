@@ -188,21 +188,39 @@ __device__ __forceinline__ float plane_root(float4 g, const Ray& r, float t_min)
   return (den != 0.0f && t > t_min) ? t : __builtin_inff();
 }
 
-// Algorithmic work counters (the method's own count: every segment tests every
-// primitive; a shadow ray tests primitives in ascending id order up to and
-// including its first occluder).  NoCount compiles to nothing.
+// Work counters.  tests(): the method's algorithmic count (every segment
+// tests every primitive; a shadow ray tests primitives in ascending id order
+// up to and including its first occluder).  exec(): the exact ray-primitive
+// tests this code actually runs, counted once per ray whose result can still
+// matter (a live path, a shadow ray not yet blocked); pairs that a cone test
+// or a wave bound decides are not counted, and neither are lanes that only
+// run along.  NoCount compiles to nothing.
 struct NoCount {
   __device__ __forceinline__ void tests(int, int) {}
+  __device__ __forceinline__ void exec(int, int) {}
   __device__ __forceinline__ void ray(int) {}
 };
 
-enum { kCntSphereTests = 0, kCntPlaneTests, kCntPrimary, kCntReflection, kCntShadow, kNumCounts };
+enum {
+  kCntSphereTests = 0,
+  kCntPlaneTests,
+  kCntPrimary,
+  kCntReflection,
+  kCntShadow,
+  kCntExecSphere,
+  kCntExecPlane,
+  kNumCounts
+};
 
 struct Count {
-  int c[kNumCounts] = {0, 0, 0, 0, 0};
+  int c[kNumCounts] = {0, 0, 0, 0, 0, 0, 0};
   __device__ __forceinline__ void tests(int sph, int pl) {
     c[kCntSphereTests] += sph;
     c[kCntPlaneTests] += pl;
+  }
+  __device__ __forceinline__ void exec(int sph, int pl) {
+    c[kCntExecSphere] += sph;
+    c[kCntExecPlane] += pl;
   }
   __device__ __forceinline__ void ray(int kind) { c[kind] += 1; }
 };
@@ -602,9 +620,10 @@ __device__ __forceinline__ void transposed_shadow(float ocx, float ocy, float oc
 // bounded by a wave bundle, and only the spheres it may meet run the exact
 // test.  Skipped spheres are ones the exact test would reject, and the exact
 // test is the same code in every path, so all paths give the same bits.
-template <bool kFromEye = false, bool kPrefilter = true>
+template <bool kFromEye, bool kPrefilter, class Cnt>
 __device__ __forceinline__ void closest_hit(const SceneDev& s, const Ray& r, bool live,
-                                            float& t_best, int& id_best, int from_plane = -1) {
+                                            float& t_best, int& id_best, Cnt& cnt,
+                                            int from_plane = -1) {
   t_best = __builtin_inff();
   id_best = kMiss;
   const float tmin = s.t_min;
@@ -624,17 +643,21 @@ __device__ __forceinline__ void closest_hit(const SceneDev& s, const Ray& r, boo
         while (m) {
           const int k = (int)__builtin_ctzll(m);
           m &= m - 1;
-          if (wave_any(live & (cone_excess(lane_read4(a, k), r.dx, r.dy, r.dz) >= 0.0f)))
+          if (wave_any(live & (cone_excess(lane_read4(a, k), r.dx, r.dy, r.dz) >= 0.0f))) {
+            cnt.exec(live ? 1 : 0, 0);
             test_sphere_oc(lane_read(ocx, k), lane_read(ocy, k), lane_read(ocz, k),
                            lane_read(g.w, k), base + k, r, tmin, t_best, id_best);
+          }
         }
       }
     } else {
       scan_spheres(
           s.eye_cone, s.n4,
           [&](int i, float4 a) {
-            if (wave_any(live & (cone_excess(a, r.dx, r.dy, r.dz) >= 0.0f)))
+            if (wave_any(live & (cone_excess(a, r.dx, r.dy, r.dz) >= 0.0f))) {
+              cnt.exec(live ? 1 : 0, 0);
               test_sphere(ld4(s.geom, i), i, r, tmin, t_best, id_best);
+            }
           },
           [] { return false; });
     }
@@ -654,14 +677,17 @@ __device__ __forceinline__ void closest_hit(const SceneDev& s, const Ray& r, boo
         if (wb.on) cand = cand & sphere_may_meet(wb, g, s.rad[jc].x);
         uint64_t m = wave_mask(cand);
         if (kTransposedHit && n_rays * kTransHitCost < __builtin_popcountll(m) * kLaneHitCost) {
+          cnt.exec(live ? __builtin_popcountll(m) : 0, 0);
           transposed_hit(g, m, base, rays, r, tmin, t_best, id_best);
         } else if (wb.on) {
+          cnt.exec(live ? __builtin_popcountll(m) : 0, 0);
           while (m) {
             const int k = (int)__builtin_ctzll(m);
             m &= m - 1;
             test_sphere(lane_read4(g, k), base + k, r, tmin, t_best, id_best);
           }
         } else {
+          cnt.exec(live ? min(64, s.n_spheres - base) : 0, 0);
           scan_range(
               s.geom, base, min(base + 64, s.n4),
               [&](int i, float4 gi) { test_sphere(gi, i, r, tmin, t_best, id_best); },
@@ -669,11 +695,13 @@ __device__ __forceinline__ void closest_hit(const SceneDev& s, const Ray& r, boo
         }
       }
     } else {
+      cnt.exec(live ? s.n_spheres : 0, 0);
       scan_spheres(
           s.geom, s.n4, [&](int i, float4 g) { test_sphere(g, i, r, tmin, t_best, id_best); },
           [] { return false; });
     }
   }
+  cnt.exec(0, live ? s.n_planes : 0);
   for (int j = 0; j < s.n_planes; ++j) {
     float t = plane_root(ld4(s.pgeom, j), r, tmin);
     if (t < t_best && s.n_spheres + j != from_plane) {
@@ -759,6 +787,7 @@ __device__ __forceinline__ bool occluded(const SceneDev& s, int l, float4 q, con
         const int k = (int)__builtin_ctzll(m);
         m &= m - 1;
         if (wave_any(!occ & (cone_excess(lane_read4(a, k), ux, uy, uz) >= 0.0f))) {
+          cnt.exec(occ ? 0 : 1, 0);
           shadow_sphere_oc(lane_read(ocx, k), lane_read(ocy, k), lane_read(ocz, k),
                            lane_read(g.w, k), base + k, rr, lim, self, occ, first);
           if (!wave_any(!occ)) {   // every lane of the wave is occluded
@@ -787,6 +816,9 @@ __device__ __forceinline__ bool occluded(const SceneDev& s, int l, float4 q, con
       const int n_rays = __builtin_popcountll(wave_mask(!occ));
       if (kTransposedShadow &&
           n_rays * kTransShadowCost < __builtin_popcountll(m) * kLaneShadowCost) {
+        // every ray not yet blocked meets every candidate (the transposed
+        // loop does not stop a ray at its first occluder within the chunk)
+        cnt.exec(occ ? 0 : __builtin_popcountll(m), 0);
         transposed_shadow(ocx, ocy, ocz, g.w, m, base, rr, lim, self, occ, first);
         done = !wave_any(!occ);
       } else if (wc.on) {
@@ -794,6 +826,7 @@ __device__ __forceinline__ bool occluded(const SceneDev& s, int l, float4 q, con
           const int k = (int)__builtin_ctzll(m);
           m &= m - 1;
           if (wave_any(!occ & (cone_excess(lane_read4(a, k), ux, uy, uz) >= 0.0f))) {
+            cnt.exec(occ ? 0 : 1, 0);
             shadow_sphere_oc(lane_read(ocx, k), lane_read(ocy, k), lane_read(ocz, k),
                              lane_read(g.w, k), base + k, rr, lim, self, occ, first);
             if (!wave_any(!occ)) {   // every lane of the wave is occluded
@@ -806,8 +839,10 @@ __device__ __forceinline__ bool occluded(const SceneDev& s, int l, float4 q, con
         scan_range(
             cones, base, min(base + 64, s.n4),
             [&](int i, float4 ai) {
-              if (wave_any(!occ & (cone_excess(ai, ux, uy, uz) >= 0.0f)))
+              if (wave_any(!occ & (cone_excess(ai, ux, uy, uz) >= 0.0f))) {
+                cnt.exec(occ ? 0 : 1, 0);
                 shadow_sphere(ld4(s.geom, i), i, rr, lim, self, occ, first);
+              }
             },
             [&] { return !wave_any(!occ); });
         done = !wave_any(!occ);
@@ -817,8 +852,10 @@ __device__ __forceinline__ bool occluded(const SceneDev& s, int l, float4 q, con
     scan_spheres(
         cones, s.n4,
         [&](int i, float4 a) {
-          if (!kPrefilter || wave_any(!occ & (cone_excess(a, ux, uy, uz) >= 0.0f)))
+          if (!kPrefilter || wave_any(!occ & (cone_excess(a, ux, uy, uz) >= 0.0f))) {
+            cnt.exec((occ || i >= s.n_spheres) ? 0 : 1, 0);   // padding spheres are no work
             shadow_sphere(ld4(s.geom, i), i, rr, lim, self, occ, first);
+          }
         },
         [&] { return !wave_any(!occ); });   // every lane of the wave is occluded
   }
@@ -831,6 +868,7 @@ __device__ __forceinline__ bool occluded(const SceneDev& s, int l, float4 q, con
     // computed by every lane and combined bitwise: a short-circuit here
     // becomes an exec-mask branch around the root, which cost more
     const float tp = plane_root(ld4(s.pgeom, j), sr, s.t_min);
+    cnt.exec(0, occ ? 0 : 1);
     const bool hit = (!occ) & (s.n_spheres + j != self) & (tp < dist);
     plane_hit = hit ? j : plane_hit;
     occ = occ | hit;
@@ -1251,9 +1289,9 @@ __device__ __forceinline__ int trace_segment(const SceneDev& s, PathState& ps, i
   float t;
   int id;
   if (kFromEye)
-    closest_hit<true, kPrefilter>(s, ps.r, alive, t, id);
+    closest_hit<true, kPrefilter>(s, ps.r, alive, t, id, cnt);
   else
-    closest_hit<false, kPrefilter>(s, ps.r, alive, t, id, ps.from_plane);
+    closest_hit<false, kPrefilter>(s, ps.r, alive, t, id, cnt, ps.from_plane);
   if (alive) {
     cnt.ray(k == 0 ? kCntPrimary : kCntReflection);
     cnt.tests(s.n_spheres, s.n_planes);

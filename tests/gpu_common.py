@@ -5,8 +5,12 @@ Parity bar (FP32 kernel vs FP64 oracle):
   * primary hit ids bit-exact on every pixel whose decision margin is at
     least GRAZING (1e-6, relative);
   * colour within COLOUR_TOL (1e-4 absolute) on every non-grazing pixel that
-    the oracle's jittered re-traces classify as well conditioned; the
-    mismatch fraction over all non-grazing pixels is reported.
+    the oracle's jittered re-traces classify as well conditioned;
+  * two ceilings per case, so that a classifier that excluded more pixels, or
+    a kernel that drifted on the pixels it does not check, cannot pass
+    silently: the share of pixels classified ill conditioned (max_ill), and
+    the share of all non-grazing pixels off by more than COLOUR_TOL
+    (max_mismatch, the mismatch fraction the colour bar reports).
 """
 
 from __future__ import annotations
@@ -20,6 +24,10 @@ import torch
 
 GRAZING = 1e-6
 COLOUR_TOL = 1e-4
+
+# Default ceilings for small scenes; full-size workloads pass their own.
+MAX_ILL = 0.10
+MAX_MISMATCH = 0.005
 
 
 def log(*a):
@@ -45,7 +53,7 @@ def gpu_render(rt, scene, cam, W, H, D, records=False, sky=None):
 
 
 def compare(oracle, scene, cam, W, H, D, gpu, pixels=None, label="", samples=1,
-            light_radius=0.0, sky=None):
+            light_radius=0.0, sky=None, max_ill=MAX_ILL, max_mismatch=MAX_MISMATCH):
     """Returns a stats dict; raises AssertionError when the parity bar fails.
     samples > 1 compares soft shadows of lights of radius light_radius; `sky`
     is the skybox [h, w, 3] both sides render with."""
@@ -76,6 +84,11 @@ def compare(oracle, scene, cam, W, H, D, gpu, pixels=None, label="", samples=1,
     assert not id_bad.any(), f"{label}: {int(id_bad.sum())} non-grazing primary id mismatches"
     assert not col_bad.any(), (f"{label}: {int(col_bad.sum())} well-conditioned pixels off by "
                                f"> {COLOUR_TOL}; max {err[checked].max():.3g}")
+    assert stats["ill_conditioned"] <= max_ill, (
+        f"{label}: {stats['ill_conditioned']:.4f} of pixels ill conditioned, ceiling {max_ill}")
+    assert stats["colour_mismatch_frac_nongrazing"] <= max_mismatch, (
+        f"{label}: {stats['colour_mismatch_frac_nongrazing']:.5f} of non-grazing pixels off by "
+        f"> {COLOUR_TOL}, ceiling {max_mismatch}")
     if "seg_id" in gpu:
         robust = checked
         assert np.array_equal(gpu["seg_id"][sel][robust], base.seg_id[robust]), "segment ids"

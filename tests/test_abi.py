@@ -155,7 +155,8 @@ def test_render_rejects_null_buffers_and_short_records(rt):
                                       C.byref(rt.rt_grads()), None) == 1
     assert rt._lib.rt_render_backward(FAKE_SCENE, C.byref(c), 8, 8, 1, 0x1000, None, None,
                                       None) == 1
-    assert rt._lib.rt_render_counts(FAKE_SCENE, C.byref(c), 8, 8, 1, None, None) == 1
+    assert rt._lib.rt_render_counts(FAKE_SCENE, C.byref(c), 8, 8, 1, None, 0, None) == 1
+    assert rt._lib.rt_render_counts(FAKE_SCENE, C.byref(c), 8, 8, 1, 0x1000, 2, None) == 1
 
 
 def test_set_sky_rejects_bad_arguments_before_any_device_call(rt):
@@ -243,3 +244,74 @@ def test_build_script_loads_without_the_library():
         "print('ok')\n")
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0 and r.stdout.strip() == "ok", r.stdout + r.stderr
+
+
+@pytest.mark.parametrize("bad", ["cpu", "float64", "list"])
+def test_binding_refuses_host_and_mistyped_buffers(rt, bad):
+    """The binding checks every caller buffer (device, dtype, contiguity, size)
+    before it calls the library: a host or float64 tensor never reaches a
+    kernel as a device pointer."""
+    import torch
+    W, H, D = 8, 4, 1
+    make = {"cpu": lambda *s: torch.zeros(*s, dtype=torch.float32),
+            "float64": lambda *s: torch.zeros(*s, dtype=torch.float64),
+            "list": lambda *s: [0.0] * int(np.prod(s))}[bad]
+    cam = Camera()
+    calls = [
+        lambda: rt.rt_render(FAKE_SCENE, cam, W, H, D, make(H, W, 3)),
+        lambda: rt.rt_render_ex(FAKE_SCENE, cam, W, H, D, make(H, W, 3), flags=0),
+        lambda: rt.rt_render_soft(FAKE_SCENE, cam, W, H, D, 8, 0.5, make(H, W, 3)),
+        lambda: rt.rt_render_counts(FAKE_SCENE, cam, W, H, D, make(7)),
+        lambda: rt.rt_render_backward(FAKE_SCENE, cam, W, H, D, make(H, W, 3), {}),
+        lambda: rt.rt_batch_create([FAKE_SCENE], [cam], [W], [H], [D], [make(H, W, 3)]),
+        lambda: rt.rt_frame_create(FAKE_SCENE, W, H, make(H, W, 3)),
+    ]
+    for i, call in enumerate(calls):
+        with pytest.raises(ValueError):
+            call()
+
+
+def test_binding_checks_scene_array_sizes(rt):
+    s = scenegen.tiny_scene(1, n_spheres=3, n_lights=1)
+    arrays = {k: getattr(s, k) for k in ("sphere_geom", "sphere_mat", "sphere_shine",
+                                         "plane_geom", "plane_mat", "plane_shine", "light")}
+    arrays["sphere_shine"] = arrays["sphere_shine"][:2]
+    with pytest.raises(ValueError, match="sphere_shine"):
+        rt._Desc(s, arrays)
+    arrays = dict(arrays, sphere_shine=s.sphere_shine, sphere_geom=s.sphere_geom[:, :3])
+    with pytest.raises(ValueError, match="sphere_geom"):
+        rt._Desc(s, arrays)
+
+
+def test_batch_tile_limit_boundary(rt):
+    """The queue numbers tiles with 32-bit integers and hands out unsigned
+    tickets up to n_tiles + grid - 1: 512 images of 16384 x 16384 make
+    exactly 2^31 one-wave tiles, one past the limit, and are refused before
+    any scene is read."""
+    n = 512
+    scenes = (C.c_void_p * n)(*([FAKE_SCENE] * n))
+    cams = (rt.rt_camera * n)(*([rt.make_camera(Camera())] * n))
+    arr = lambda v: (C.c_int32 * n)(*([v] * n))
+    outs = (C.c_void_p * n)(*([0x1000] * n))
+    b = C.c_void_p()
+    st = rt._lib.rt_batch_create(n, scenes, cams, arr(rt.RT_MAX_DIM), arr(rt.RT_MAX_DIM), arr(1),
+                                 outs, 0, None, C.byref(b))
+    assert st == rt.RT_ERR_INVALID_ARG and not b.value
+    assert "2147483648 tiles" in rt.rt_last_error()
+
+
+def test_scene_counts_rejects_null(rt):
+    assert rt._lib.rt_scene_counts(None, None, None, None) == rt.RT_ERR_INVALID_ARG
+
+
+def test_prepare_and_flags_are_checked_on_the_host(rt):
+    c = rt.make_camera(Camera())
+    assert rt._lib.rt_render_prepare(None, C.byref(c), None) == rt.RT_ERR_INVALID_ARG
+    assert rt._lib.rt_render_prepare(FAKE_SCENE, None, None) == rt.RT_ERR_INVALID_ARG
+    bad = rt.make_camera(Camera(fov_deg=0.0))
+    assert rt._lib.rt_render_prepare(FAKE_SCENE, C.byref(bad), None) == rt.RT_ERR_INVALID_ARG
+    assert rt._lib.rt_render_ex(FAKE_SCENE, C.byref(c), 8, 8, 1, 0x1000, None, None, 4,
+                                None) == rt.RT_ERR_INVALID_ARG
+    # soft renders and frames take no prepared cones
+    assert rt._lib.rt_render_soft(FAKE_SCENE, C.byref(c), 8, 8, 1, 8, 0.5, 0x1000, None,
+                                  rt.RT_RENDER_CONES_READY, None) == rt.RT_ERR_INVALID_ARG

@@ -5,7 +5,8 @@ float64 on the oracle's own records, pinned by central differences of the C
 oracle (tests/test_oracle_grad.py).  Both sides get the same dLoss/dRGB,
 non-zero only on pixels where the GPU's records equal the oracle's, that the
 oracle classifies well conditioned, and that are at least 2 px from a
-primary-id edge.  Bar: relative L2 error per parameter group <= 1e-3.
+primary-id edge.  Bar: relative L2 error per parameter group <= 1e-3, and
+every element within 1e-3 of the group's largest reference magnitude.
 """
 
 import numpy as np
@@ -21,6 +22,7 @@ pytestmark = pytest.mark.gpu
 
 GROUPS = ("albedo", "refl", "center", "light_pos", "light_int")
 REL_TOL = 1e-3
+ELEM_TOL = 1e-3   # max |g - ref| over a group, relative to max |ref| of the group
 
 
 @pytest.fixture(scope="module")
@@ -72,16 +74,19 @@ def reference_check(rt, oracle_mod, scene, cam, W, H, D, target, label, sky=None
                             sky=sky)["grads"]
     o0, d0 = oracle_mod.camera_rays(cam, W, H, np.arange(W * H))
     ref = grad_ref.vjp(scene, o0, d0, base.seg_id, base.lit, D, grad_rgb, sky)
-    errs = {}
+    errs, elem = {}, {}
     for k in GROUPS:
         g = res["checkpoint"][k]
         assert np.isfinite(g).all(), k
         assert np.array_equal(g, res["recompute"][k]), f"{k}: checkpoint and recompute differ"
         denom = max(np.linalg.norm(ref[k]), 1e-30)
         errs[k] = float(np.linalg.norm(g - ref[k]) / denom)
-    log("grad parity", label, "mask", float(mask.mean()), errs)
+        # element-wise: no single parameter may hide inside its group's norm
+        elem[k] = float(np.abs(g - ref[k]).max() / max(np.abs(ref[k]).max(), 1e-30))
+    log("grad parity", label, "mask", float(mask.mean()), "rel L2", errs, "elementwise", elem)
     for k in GROUPS:
         assert errs[k] <= REL_TOL, (label, k, errs[k])
+        assert elem[k] <= ELEM_TOL, (label, k, elem[k])
     return res["checkpoint"], ref, mask, grad_rgb
 
 

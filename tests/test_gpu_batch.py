@@ -101,6 +101,41 @@ def test_batch_image_matches_oracle(rt, oracle_mod):
             h.close()
 
 
+# The four densest scenes of the 64-scene batch (about 900 spheres in the small
+# box): index, rows sampled every `step`.
+DENSE_BATCH_SCENES = ((18, 16), (3, 16), (8, 16), (40, 1))
+
+
+def test_workload3_densest_scenes_match_oracle(rt, oracle_mod):
+    """The batch's own output for its densest scenes, where brute force is
+    costliest (about 900 spheres), against the FP64 oracle on sampled rows;
+    primary ids come from a single render, which the batch equals bit for bit."""
+    wls = scenegen.make_batch()
+    handles = [rt.SceneHandle(w.scene) for w in wls]
+    try:
+        b, outs = make_batch(rt, wls, handles, True)
+        rt.rt_batch_launch(b)
+        torch.cuda.synchronize()
+        for i, step in DENSE_BATCH_SCENES:
+            wl = wls[i]
+            log("case batch scene", i, wl.name, "spheres", wl.scene.n_spheres)
+            ids = torch.empty((wl.H, wl.W), dtype=torch.int32, device="cuda")
+            rgb = torch.empty((wl.H, wl.W, 3), device="cuda")
+            rt.rt_render(handles[i].handle, wl.camera, wl.W, wl.H, wl.depth, rgb, ids)
+            torch.cuda.synchronize()
+            assert torch.equal(rgb, outs[i])
+            g = dict(rgb=outs[i].cpu().numpy().reshape(-1, 3).astype(np.float64),
+                     ids=ids.cpu().numpy().reshape(-1))
+            rows = np.unique(np.concatenate([np.arange(0, wl.H, step), [wl.H - 1]]))
+            pixels = (rows[:, None] * wl.W + np.arange(wl.W)[None, :]).reshape(-1)
+            compare(oracle_mod, wl.scene, wl.camera, wl.W, wl.H, wl.depth, g, pixels=pixels,
+                    label=f"batch dense {i}", max_ill=0.30, max_mismatch=0.01)
+        rt.rt_batch_destroy(b)
+    finally:
+        for h in handles:
+            h.close()
+
+
 def test_scene_update_between_replays(rt):
     wls = small_batch()[:3]
     handles = [rt.SceneHandle(w.scene) for w in wls]

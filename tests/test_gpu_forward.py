@@ -27,7 +27,8 @@ def test_workload0_full_frame(rt, oracle_mod, seed):
     wl = scenegen.make_workload(0, seed)
     log("case workload0", wl.scene.digest(), "seed", seed)
     g = gpu_render(rt, wl.scene, wl.camera, wl.W, wl.H, wl.depth, records=True)
-    compare(oracle_mod, wl.scene, wl.camera, wl.W, wl.H, wl.depth, g, label=f"w0 seed={seed}")
+    compare(oracle_mod, wl.scene, wl.camera, wl.W, wl.H, wl.depth, g, label=f"w0 seed={seed}",
+            **CEILINGS[0])
 
 
 EDGE_CASES = [
@@ -95,6 +96,16 @@ def test_scene_update_in_place(rt, oracle_mod):
     compare(oracle_mod, s2, wl.camera, wl.W, wl.H, wl.depth, g, label="updated")
 
 
+# Ceilings per workload: the share of pixels the oracle classifies ill
+# conditioned, and the share of non-grazing pixels whose colour is off by more
+# than 1e-4 (the mismatch fraction).  Measured values sit well below them
+# (see the design notes); a drifting classifier or kernel trips them.
+CEILINGS = {0: dict(max_ill=0.04, max_mismatch=0.001),
+            1: dict(max_ill=0.12, max_mismatch=0.0005),
+            2: dict(max_ill=0.25, max_mismatch=0.005),
+            4: dict(max_ill=0.08, max_mismatch=0.0005)}
+
+
 @pytest.mark.parametrize("config,row_step", [(1, 1), (2, 8), (4, 1)])
 def test_full_size_sampled_rows(rt, oracle_mod, config, row_step):
     """Full-size workloads rendered whole on the GPU, in the launch the
@@ -106,7 +117,7 @@ def test_full_size_sampled_rows(rt, oracle_mod, config, row_step):
     rows = np.unique(np.concatenate([rows, [wl.H - 1]]))
     pixels = (rows[:, None] * wl.W + np.arange(wl.W)[None, :]).reshape(-1)
     compare(oracle_mod, wl.scene, wl.camera, wl.W, wl.H, wl.depth, g, pixels=pixels,
-            label=wl.name)
+            label=wl.name, **CEILINGS[config])
 
 
 @pytest.mark.parametrize("config", [0, 1, 4])
@@ -125,6 +136,27 @@ def test_work_counters_match_oracle(rt, oracle_mod, config):
     assert got["primary_rays"] == want["primary_rays"] == wl.W * wl.H
     for k in want:
         assert abs(got[k] - want[k]) <= 1e-3 * max(want[k], 1), (k, got[k], want[k])
+    # the culled kernel runs far fewer exact tests than the method counts
+    assert 0 < got["exec_sphere_tests"] < got["sphere_tests"]
+    assert 0 < got["exec_plane_tests"] <= got["plane_tests"]
+
+
+@pytest.mark.parametrize("config", [0, 1, 2, 4])
+def test_brute_force_kernel_executes_the_method_count(rt, config):
+    """Without the cone tests and wave bounds, the kernel executes exactly the
+    tests the method counts (every segment every primitive, a shadow ray up
+    to its first occluder): executed == algorithmic, bit for bit."""
+    wl = scenegen.make_workload(config)
+    with rt.SceneHandle(wl.scene) as h:
+        c = rt.render_counts(h.handle, wl.camera, wl.W, wl.H, wl.depth,
+                             flags=rt.RT_RENDER_NO_PREFILTER)
+        culled = rt.render_counts(h.handle, wl.camera, wl.W, wl.H, wl.depth)
+    log("brute-force counts", wl.name, c)
+    assert c["exec_sphere_tests"] == c["sphere_tests"]
+    assert c["exec_plane_tests"] == c["plane_tests"]
+    # the culling changes what is executed, not the method's count
+    for k in ("sphere_tests", "plane_tests", "primary_rays", "reflection_rays", "shadow_rays"):
+        assert c[k] == culled[k], k
 
 
 ALL_FLAGS = (0, 1)   # with and without the cone prefilters
@@ -225,3 +257,24 @@ def test_wave_bounds_change_no_bits_batch_scenes(rt):
                 out.append((rgb.cpu(), ids.cpu(), rec.buf.cpu()))
         for a, b2 in zip(out[0], out[1]):
             assert torch.equal(a, b2), i
+
+
+@pytest.mark.parametrize("config", [0, 1])
+def test_prepared_cones_give_the_same_bits(rt, config):
+    """rt_render_prepare followed by rt_render_ex(RT_RENDER_CONES_READY) is
+    rt_render split in its two launches: the same image and ids."""
+    wl = scenegen.make_workload(config)
+    W, H, D = wl.W, wl.H, wl.depth
+    with rt.SceneHandle(wl.scene) as h:
+        a = torch.empty((H, W, 3), device="cuda")
+        ia = torch.empty((H, W), dtype=torch.int32, device="cuda")
+        rt.rt_render(h.handle, wl.camera, W, H, D, a, ia)
+        # another camera's cones in between, then the prepared render
+        other = rt.render(h.handle, Camera(yaw_deg=40.0), W, H, D)
+        rt.rt_render_prepare(h.handle, wl.camera)
+        b = torch.empty_like(a)
+        ib = torch.empty_like(ia)
+        rt.rt_render_ex(h.handle, wl.camera, W, H, D, b, ib, None, rt.RT_RENDER_CONES_READY)
+        torch.cuda.synchronize()
+        del other
+    assert torch.equal(a, b) and torch.equal(ia, ib)
