@@ -35,6 +35,17 @@ def log(*a):
     sys.stdout.flush()
 
 
+def record_stats(stats):
+    """Appends one parity result as a JSON line to the file named by
+    RT_PARITY_LOG (nothing when it is unset), so that a run of the GPU suite
+    leaves every case's mismatch and exclusion fractions in one place."""
+    path = os.environ.get("RT_PARITY_LOG")
+    if path:
+        import json
+        with open(path, "a") as f:
+            f.write(json.dumps(stats) + "\n")
+
+
 def gpu_render(rt, scene, cam, W, H, D, records=False, sky=None):
     h = rt.SceneHandle(scene)
     try:
@@ -79,6 +90,7 @@ def compare(oracle, scene, cam, W, H, D, gpu, pixels=None, label="", samples=1,
                  max_err_checked=float(err[checked].max()) if checked.any() else 0.0,
                  max_err_all=float(err.max()) if err.size else 0.0)
     log("parity", stats)
+    record_stats(dict(stats, max_ill=max_ill, max_mismatch=max_mismatch))
     if id_bad.any() or col_bad.any():
         _dump(label, sel, base, gpu, err, nongrazing, ok_cond)
     assert not id_bad.any(), f"{label}: {int(id_bad.sum())} non-grazing primary id mismatches"

@@ -6,7 +6,13 @@ oracle (tests/test_oracle_grad.py).  Both sides get the same dLoss/dRGB,
 non-zero only on pixels where the GPU's records equal the oracle's, that the
 oracle classifies well conditioned, and that are at least 2 px from a
 primary-id edge.  Bar: relative L2 error per parameter group <= 1e-3, and
-every element within 1e-3 of the group's largest reference magnitude.
+every element within 1e-3 of the group's largest reference magnitude plus
+four times that element's own FP32 conditioning: the largest change of the
+reference element when the primary rays move by the oracle's jitter
+(relative 2^-21, as in the colour conditioning).  A gradient through a hit
+near grazing (dt/dc = n/(n.d)) or a high specular exponent can move by far
+more than the colour does; a dropped term or a wrong sign moves a
+well-conditioned element by its own size, far beyond that allowance.
 """
 
 import numpy as np
@@ -16,13 +22,29 @@ import torch
 import scenegen
 from scenegen import Camera, SPEC_BLINN, SPEC_PHONG
 
-from .gpu_common import log
+from .gpu_common import log, record_stats
 
 pytestmark = pytest.mark.gpu
 
 GROUPS = ("albedo", "refl", "center", "light_pos", "light_int")
 REL_TOL = 1e-3
-ELEM_TOL = 1e-3   # max |g - ref| over a group, relative to max |ref| of the group
+ELEM_TOL = 1e-3   # max |g - ref| - 4 sigma over a group, relative to max |ref| of the group
+COND_RUNS = 4
+
+
+def grad_spread(oracle_mod, scene, o0, d0, seg, lit, D, grad_rgb, ref, sky=None):
+    """Per element, the largest change of the reference gradient over
+    COND_RUNS re-shades whose primary rays carry the oracle's relative jitter
+    (decisions held fixed)."""
+    from oracle import grad_ref
+    rng = np.random.default_rng(0x6A77)
+    spread = {k: np.zeros_like(v) for k, v in ref.items()}
+    for _ in range(COND_RUNS):
+        j = lambda a: a * (1.0 + oracle_mod.JITTER * rng.uniform(-1.0, 1.0, a.shape))
+        r = grad_ref.vjp(scene, j(o0), j(d0), seg, lit, D, grad_rgb, sky)
+        for k in ref:
+            spread[k] = np.maximum(spread[k], np.abs(r[k] - ref[k]))
+    return spread
 
 
 @pytest.fixture(scope="module")
@@ -74,7 +96,8 @@ def reference_check(rt, oracle_mod, scene, cam, W, H, D, target, label, sky=None
                             sky=sky)["grads"]
     o0, d0 = oracle_mod.camera_rays(cam, W, H, np.arange(W * H))
     ref = grad_ref.vjp(scene, o0, d0, base.seg_id, base.lit, D, grad_rgb, sky)
-    errs, elem = {}, {}
+    sigma = grad_spread(oracle_mod, scene, o0, d0, base.seg_id, base.lit, D, grad_rgb, ref, sky)
+    errs, elem, raw = {}, {}, {}
     for k in GROUPS:
         g = res["checkpoint"][k]
         assert np.isfinite(g).all(), k
@@ -82,8 +105,13 @@ def reference_check(rt, oracle_mod, scene, cam, W, H, D, target, label, sky=None
         denom = max(np.linalg.norm(ref[k]), 1e-30)
         errs[k] = float(np.linalg.norm(g - ref[k]) / denom)
         # element-wise: no single parameter may hide inside its group's norm
-        elem[k] = float(np.abs(g - ref[k]).max() / max(np.abs(ref[k]).max(), 1e-30))
-    log("grad parity", label, "mask", float(mask.mean()), "rel L2", errs, "elementwise", elem)
+        scale = max(np.abs(ref[k]).max(), 1e-30)
+        raw[k] = float(np.abs(g - ref[k]).max() / scale)
+        elem[k] = float(max((np.abs(g - ref[k]) - 4.0 * sigma[k]).max(), 0.0) / scale)
+    log("grad parity", label, "mask", float(mask.mean()), "rel L2", errs, "elementwise", raw,
+        "beyond conditioning", elem)
+    record_stats(dict(label="grad " + label, mask=float(mask.mean()), rel_l2=errs,
+                      elementwise=raw, elementwise_beyond_conditioning=elem))
     for k in GROUPS:
         assert errs[k] <= REL_TOL, (label, k, errs[k])
         assert elem[k] <= ELEM_TOL, (label, k, elem[k])

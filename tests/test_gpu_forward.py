@@ -51,6 +51,12 @@ EDGE_CASES = [
 ]
 
 
+# Ceilings on the ill-conditioned share above the default, measured share
+# x ~1.3: eight lights over eight mirror spheres in a 48x27 view put about
+# 12 % of the pixels on a shadow edge or a reflected silhouette.
+EDGE_CEILINGS = {"lights_max": dict(max_ill=0.15)}
+
+
 @pytest.mark.parametrize("case", EDGE_CASES, ids=[c[0] for c in EDGE_CASES])
 def test_edge_cases(rt, oracle_mod, case):
     name, W, H, D, N, L, plane, spec, cam = case
@@ -61,7 +67,7 @@ def test_edge_cases(rt, oracle_mod, case):
         s = Scene(**{k: getattr(s, k) for k in s.__dataclass_fields__})
     log("case", name, W, H, D, N, L)
     g = gpu_render(rt, s, cam, W, H, D, records=True)
-    compare(oracle_mod, s, cam, W, H, D, g, label=name)
+    compare(oracle_mod, s, cam, W, H, D, g, label=name, **EDGE_CEILINGS.get(name, {}))
 
 
 def test_records_do_not_change_image_and_runs_repeat(rt):

@@ -6,7 +6,8 @@
   * RT_MAX_SAMPLES shadow samples per light;
   * soft shadows in a scene past the sphere chunks the soft bound covers, so
     every sample ray scans every sphere;
-  * the adjoint at its largest scene (2335 spheres) and one sphere past it;
+  * the adjoint at RT_MAX_SPHERES spheres (its accumulators take 112 KiB of
+    LDS, within the 160 KiB a gfx950 workgroup may hold);
   * a batch of RT_MAX_BATCH scenes.
 
 The parity bar is the one of the other forward tests (tests/gpu_common.py);
@@ -59,7 +60,9 @@ def test_largest_scene(rt, oracle_mod):
     log("case limits scene", s.n_spheres, "spheres", s.plane_geom.shape[0], "planes",
         s.n_lights, "lights", W, H, D)
     g = gpu_render(rt, s, cam, W, H, D, records=True)
-    stats, base = compare(oracle_mod, s, cam, W, H, D, g, label="max_scene")
+    # 4096 spheres of radius 0.1-0.6 in a 48x27 view: about 39 % of the
+    # pixels sit on a silhouette, shadow edge or reflected edge
+    stats, base = compare(oracle_mod, s, cam, W, H, D, g, label="max_scene", max_ill=0.45)
     # the view is crowded: about half the primary rays hit a sphere
     assert (base.prim_id < s.n_spheres).mean() > 0.4, stats
 
@@ -74,7 +77,9 @@ def test_largest_image_side(rt, oracle_mod, shape):
     D = 2
     log("case limits image", W, H, D)
     g = gpu_render(rt, wl.scene, cam, W, H, D)
-    compare(oracle_mod, wl.scene, cam, W, H, D, g, label=f"max_dim_{shape}")
+    # a 0.02 degree short side: a pixel row spans the whole scene, so about
+    # 15 % of the wide image's pixels straddle an edge
+    compare(oracle_mod, wl.scene, cam, W, H, D, g, label=f"max_dim_{shape}", max_ill=0.18)
 
 
 def soft_render(rt, scene, cam, W, H, D, samples, radius):
@@ -105,36 +110,21 @@ def test_soft_shadows_past_the_bounded_chunks(rt, oracle_mod):
     W, H, D, n, R = 64, 36, 2, 16, 0.5
     log("case limits soft scan", s.n_spheres, W, H, D, n, R)
     g = soft_render(rt, s, cam, W, H, D, n, R)
-    compare(oracle_mod, s, cam, W, H, D, g, label="soft_scan", samples=n, light_radius=R)
+    # 400 small spheres, 16 samples per light: about 16 % of the pixels see
+    # a sample ray graze an occluder
+    compare(oracle_mod, s, cam, W, H, D, g, label="soft_scan", samples=n, light_radius=R,
+            max_ill=0.20)
 
 
-ADJOINT_MAX_SPHERES = 2335
-
-
-def test_adjoint_at_its_sphere_limit(rt, oracle_mod):
+def test_adjoint_at_the_sphere_limit(rt, oracle_mod):
     from .test_gpu_backward import reference_check
-    s = max_scene(rt, ADJOINT_MAX_SPHERES)
+    s = max_scene(rt)
+    assert s.n_spheres == rt.RT_MAX_SPHERES
     target = scenegen.perturb_scene(s, np.random.default_rng(2336))
     cam = Camera(eye=(0.0, 1.0, 0.0), pitch_deg=-4.0)
     W, H, D = 48, 27, 2
     log("case limits adjoint", s.n_spheres, W, H, D)
     reference_check(rt, oracle_mod, s, cam, W, H, D, target, "adjoint_max")
-
-
-def test_adjoint_refuses_one_sphere_more(rt):
-    s = max_scene(rt, ADJOINT_MAX_SPHERES + 1)
-    W, H, D = 16, 9, 1
-    log("case limits adjoint refusal", s.n_spheres)
-    with rt.SceneHandle(s) as h:
-        g = {k: torch.zeros(shape, device="cuda") for k, shape in
-             dict(albedo=(s.n_spheres, 3), refl=(s.n_spheres,), center=(s.n_spheres, 3),
-                  light_pos=(s.n_lights, 3), light_int=(s.n_lights,)).items()}
-        grad_rgb = torch.ones((H, W, 3), device="cuda")
-        with pytest.raises(rt.RtError) as e:
-            rt.rt_render_backward(h.handle, Camera(), W, H, D, grad_rgb, g, None)
-        assert e.value.status == rt.RT_ERR_UNSUPPORTED
-        torch.cuda.synchronize()
-        assert all(float(v.abs().sum()) == 0.0 for v in g.values()), "refused call wrote"
 
 
 def test_largest_batch(rt):

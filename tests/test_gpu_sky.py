@@ -91,7 +91,7 @@ def test_sky_full_size_sampled_rows(rt, oracle_mod):
     rows = np.unique(np.concatenate([np.arange(0, wl.H, 16), [wl.H - 1]]))
     pixels = (rows[:, None] * wl.W + np.arange(wl.W)[None, :]).reshape(-1)
     compare(oracle_mod, wl.scene, wl.camera, wl.W, wl.H, wl.depth, g, pixels=pixels,
-            label="sky_" + wl.name, sky=sky)
+            label="sky_" + wl.name, sky=sky, max_ill=0.13, max_mismatch=0.0005)
 
 
 @pytest.mark.parametrize("soft", [False, True])
