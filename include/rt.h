@@ -273,8 +273,9 @@ rt_status rt_render_counts(rt_scene scene, const rt_camera* cam, int32_t W, int3
  * per-wave gradient accumulators (7 N + 4 L + 4 floats) live in LDS: up to
  * 2335 spheres within 64 KiB per workgroup (four waves each for small
  * scenes), beyond that one wave per workgroup with up to the device's LDS
- * per workgroup (160 KiB on gfx950: every scene up to RT_MAX_SPHERES); a
- * scene that does not fit returns RT_ERR_UNSUPPORTED and writes nothing.
+ * per workgroup (160 KiB on gfx950: every scene up to RT_MAX_SPHERES, whose
+ * accumulators take 112 KiB); a scene that does not fit returns
+ * RT_ERR_UNSUPPORTED and writes nothing.
  * No allocation; capture-safe.  With
  * rec == NULL the re-trace first rewrites the scene's eye-cone table, so it
  * must not overlap other renders of the same scene (see rt_render); the
@@ -290,7 +291,8 @@ typedef struct rt_batch_s* rt_batch;
  * depths (each image exactly as rt_render would), captured in a HIP graph.
  * Builds the tile table (largest estimated cost first), picks the launch
  * shape (autotuned once per problem signature when `autotune` is non-zero,
- * which runs and synchronises on `stream`; cached in memory), allocates the
+ * which runs and synchronises on `stream`; cached in memory and in the JSON
+ * file of rt_tune_cache_get, so later processes skip the timing), allocates the
  * queue counter and captures the graph.  rgb_out[i] is device float32
  * [H[i]][W[i]][3].  Sizes, depths, cameras and the total tile count (at most
  * 2^31 - 1 tiles of 64 pixels, the queue's 32-bit tile numbers) are checked
@@ -325,6 +327,29 @@ rt_status rt_batch_counts(rt_batch batch, int64_t* counts, void* stream);
 rt_status rt_batch_shape(rt_batch batch, int32_t* workgroups, int32_t* tile_w, int32_t* tile_h);
 
 rt_status rt_batch_destroy(rt_batch batch);
+
+/* The batch autotuner's cache.  A key is the device's architecture name and
+ * compute-unit count followed by the batch signature (every job's W, H,
+ * depth, sphere and light count and skybox flag); rt_batch_tune_key gives a
+ * batch's key (a NUL-terminated copy of at most cap - 1 bytes into buf, and
+ * its full length into *len).  Entries live in memory and in a JSON file:
+ * $RT_TUNE_CACHE if set (empty: memory only), else
+ * $XDG_CACHE_HOME/rtmi/tune.json, else $HOME/.cache/rtmi/tune.json, holding a
+ * 64-bit FNV-1a digest of each key and its shape.  rt_batch_create with
+ * autotune looks the key up before timing and stores what it timed.
+ * rt_tune_cache_get sets *found to 1 and the shape (as rt_batch_shape gives
+ * it) on a hit, else 0.  rt_tune_cache_put stores a shape the tuner could
+ * have picked (tile_w 8, 16 or 64 columns, 64 / tile_w x 1, 2 or 4 rows,
+ * 1 to 2^20 workgroups), else RT_ERR_INVALID_ARG; a file that cannot be
+ * written gives RT_ERR_UNSUPPORTED (the entry stays in memory).
+ * rt_tune_cache_forget drops the memory entries, so that the next lookup
+ * reads the file.  A file entry that does not parse, or holds a shape
+ * outside the tuner's candidates, is ignored. */
+rt_status rt_batch_tune_key(rt_batch batch, char* buf, int64_t cap, int64_t* len);
+rt_status rt_tune_cache_get(const char* key, int32_t* workgroups, int32_t* tile_w,
+                            int32_t* tile_h, int32_t* found);
+rt_status rt_tune_cache_put(const char* key, int32_t workgroups, int32_t tile_w, int32_t tile_h);
+rt_status rt_tune_cache_forget(void);
 
 /* ---- Interactive per-frame path ------------------------------------------
  * The paper's GUI loop streams the camera, the ray-tracing properties (shadow

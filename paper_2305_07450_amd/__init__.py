@@ -111,6 +111,11 @@ _sig = {
     "rt_batch_shape": (C.c_int, [_vp, C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_i32)]),
     "rt_batch_counts": (C.c_int, [_vp, _vp, _vp]),
     "rt_batch_destroy": (C.c_int, [_vp]),
+    "rt_batch_tune_key": (C.c_int, [_vp, C.c_char_p, C.c_int64, C.POINTER(C.c_int64)]),
+    "rt_tune_cache_get": (C.c_int, [C.c_char_p, C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_i32),
+                                    C.POINTER(_i32)]),
+    "rt_tune_cache_put": (C.c_int, [C.c_char_p, _i32, _i32, _i32]),
+    "rt_tune_cache_forget": (C.c_int, []),
     "rt_frame_create": (C.c_int, [_vp, C.POINTER(rt_frame_desc), C.POINTER(_vp)]),
     "rt_frame_submit": (C.c_int, [_vp, C.POINTER(rt_frame_input), _vp]),
     "rt_frame_result": (C.c_int, [_vp, C.POINTER(_vp)]),
@@ -434,6 +439,30 @@ def rt_batch_shape(batch: int):
 
 def rt_batch_destroy(batch: int):
     _check(_lib.rt_batch_destroy(batch))
+
+
+def rt_batch_tune_key(batch: int) -> str:
+    n = C.c_int64()
+    _check(_lib.rt_batch_tune_key(batch, None, 0, C.byref(n)))
+    buf = C.create_string_buffer(n.value + 1)
+    _check(_lib.rt_batch_tune_key(batch, buf, n.value + 1, C.byref(n)))
+    return buf.value.decode()
+
+
+def rt_tune_cache_get(key: str):
+    """(workgroups, tile_w, tile_h) cached for `key`, or None."""
+    g, tw, th, found = _i32(), _i32(), _i32(), _i32()
+    _check(_lib.rt_tune_cache_get(key.encode(), C.byref(g), C.byref(tw), C.byref(th),
+                                  C.byref(found)))
+    return (g.value, tw.value, th.value) if found.value else None
+
+
+def rt_tune_cache_put(key: str, workgroups: int, tile_w: int, tile_h: int):
+    _check(_lib.rt_tune_cache_put(key.encode(), workgroups, tile_w, tile_h))
+
+
+def rt_tune_cache_forget():
+    _check(_lib.rt_tune_cache_forget())
 
 
 def rt_frame_create(handle: int, W: int, H: int, rgb_out: torch.Tensor, soft: bool = False,

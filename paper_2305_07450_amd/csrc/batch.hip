@@ -18,6 +18,7 @@
 #include <type_traits>
 #include <mutex>
 #include <new>
+#include <string.h>
 #include <string>
 #include <vector>
 
@@ -40,11 +41,7 @@ struct TileRef {
   int tile;
 };
 
-struct Shape {
-  int waves;   // wave64s per workgroup
-  int wave_w;  // pixel columns per wave (wave_w * wave_h = 64)
-  int grid;    // persistent workgroups
-};
+using Shape = TunedShape;
 
 __global__ void reset_counter_kernel(unsigned int* counter) { *counter = 0u; }
 
@@ -149,12 +146,10 @@ struct rt_batch_s {
   bool any_sky = false;          // some job's scene has a skybox
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  std::string tune_key;          // autotune cache key of this batch
 };
 
 namespace {
-
-std::mutex g_tune_mu;
-std::map<std::string, Shape> g_tune_cache;
 
 rt_status err(rt_status st, const std::string& m) {
   set_error(m);
@@ -211,8 +206,10 @@ hipError_t launch_batch(rt_batch_s* b, hipStream_t stream,
   return hipGetLastError();
 }
 
-std::string signature(const rt_batch_s* b) {
-  std::string s = std::to_string(b->n);
+// Autotune cache key: the device's architecture and compute-unit count, then
+// every job's size, depth, sphere and light count and skybox flag.
+std::string signature(const rt_batch_s* b, const std::string& arch, int cus) {
+  std::string s = arch + ":" + std::to_string(cus) + "cu:" + std::to_string(b->n);
   for (const BatchJob& j : b->host_jobs)
     s += ":" + std::to_string(j.c.W) + "x" + std::to_string(j.c.H) + "d" +
          std::to_string(j.depth) + "n" + std::to_string(j.s.n_spheres) + "l" +
@@ -369,22 +366,17 @@ rt_status batch_create(int32_t n, const rt_scene* scenes, const rt_camera* cams,
   if (e != hipSuccess) return hip_fail(e, "batch allocation");
   Shape sh{4, 8, cus * 4};
   rt_status st = RT_OK;
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, dev);
+  if (e != hipSuccess) return hip_fail(e, "device properties");
+  b->tune_key = signature(b, prop.gcnArchName, cus);
   if (autotune_flag) {
-    const std::string key = signature(b);
-    bool hit = false;
-    {
-      std::lock_guard<std::mutex> lk(g_tune_mu);
-      auto it = g_tune_cache.find(key);
-      if (it != g_tune_cache.end()) {
-        sh = it->second;
-        hit = true;
-      }
-    }
-    if (!hit) {
+    if (!tune_cache_get(b->tune_key, &sh)) {
       st = autotune(b, cus, stream, &sh);
       if (st != RT_OK) return st;
-      std::lock_guard<std::mutex> lk(g_tune_mu);
-      g_tune_cache[key] = sh;
+      // a cache file that cannot be written only costs the next process a
+      // re-tune
+      (void)tune_cache_put(b->tune_key, sh);
     }
   }
   e = upload_shape(b, sh, stream);
@@ -463,6 +455,17 @@ rt_status rt_batch_shape(rt_batch b, int32_t* workgroups, int32_t* tile_w, int32
   if (workgroups) *workgroups = b->shape.grid;
   if (tile_w) *tile_w = b->shape.wave_w;
   if (tile_h) *tile_h = (64 / b->shape.wave_w) * b->shape.waves;
+  return RT_OK;
+}
+
+rt_status rt_batch_tune_key(rt_batch b, char* buf, int64_t cap, int64_t* len) {
+  if (!b) return err(RT_ERR_INVALID_ARG, "batch is NULL");
+  if (len) *len = (int64_t)b->tune_key.size();
+  if (buf && cap > 0) {
+    const size_t n = std::min<size_t>((size_t)cap - 1, b->tune_key.size());
+    memcpy(buf, b->tune_key.data(), n);
+    buf[n] = '\0';
+  }
   return RT_OK;
 }
 

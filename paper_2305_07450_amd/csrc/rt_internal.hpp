@@ -111,6 +111,22 @@ hipError_t launch_counts(const SceneDev& s, const CameraDev& c, int depth,
 bool adjoint_supported(int n_spheres, int device);
 int adjoint_max_spheres(int device);
 
+// Launch shape of a batch: wave64s per workgroup, pixel columns per wave
+// (columns x rows = 64) and persistent workgroups.
+struct TunedShape {
+  int waves;
+  int wave_w;
+  int grid;
+};
+// One of the shapes the batch autotuner times.
+bool tuned_shape_valid(const TunedShape& s);
+// Autotune cache (memory, then the JSON file): true and *out on a hit.
+bool tune_cache_get(const std::string& key, TunedShape* out);
+// Stores an entry in memory and in the file; false if the file could not be
+// written (the memory entry is kept) or the shape is not valid.
+bool tune_cache_put(const std::string& key, const TunedShape& s);
+void tune_cache_forget_memory();
+
 // partials: [blocks][grad_stride] floats of device memory (the scene's own),
 // every row written before it is read.
 hipError_t launch_backward(const rt_scene_s& sc, const CameraDev& c, int depth,

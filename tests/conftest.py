@@ -18,3 +18,12 @@ def oracle_mod():
     import oracle
     oracle.build()
     return oracle
+
+
+@pytest.fixture(scope="session", autouse=True)
+def _private_tune_cache(tmp_path_factory):
+    """Batches the tests autotune store their shapes in a file of this test
+    session, not in the user's cache directory."""
+    if "RT_TUNE_CACHE" not in os.environ:
+        os.environ["RT_TUNE_CACHE"] = str(tmp_path_factory.mktemp("tune") / "tune.json")
+    yield

@@ -80,6 +80,54 @@ def test_small_batch_bit_exact(rt, autotune):
             h.close()
 
 
+def test_autotune_cache_persists_the_timed_shape(rt, tmp_path, monkeypatch):
+    """A tuned batch stores its shape under its key in the JSON file; another
+    process reads it; a new batch of the same signature takes the stored
+    shape instead of timing (a planted shape shows which), with the same
+    images."""
+    import json
+    import os
+    import subprocess
+    import sys
+    monkeypatch.setenv("RT_TUNE_CACHE", str(tmp_path / "tune.json"))
+    rt.rt_tune_cache_forget()
+    wls = small_batch()
+    handles = [rt.SceneHandle(w.scene) for w in wls]
+    try:
+        ref = single_images(rt, wls, handles)
+        b, outs = make_batch(rt, wls, handles, True)
+        key, shape = rt.rt_batch_tune_key(b), rt.rt_batch_shape(b)
+        rt.rt_batch_destroy(b)
+        arch = torch.cuda.get_device_properties(0).gcnArchName
+        log("tuned", shape, "key", key[:80])
+        assert key.startswith(arch + ":")
+        assert rt.rt_tune_cache_get(key) == shape
+        code = ("import sys, paper_2305_07450_amd as rt; "
+                "print(rt.rt_tune_cache_get(sys.argv[1]))")
+        root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+        child = subprocess.run([sys.executable, "-c", code, key], cwd=root, env=dict(os.environ),
+                               capture_output=True, text=True, timeout=300)
+        assert child.returncode == 0, child.stderr
+        assert child.stdout.strip().splitlines()[-1] == str(shape)
+        planted = (96, 64, 4) if shape != (96, 64, 4) else (160, 8, 16)
+        rt.rt_tune_cache_put(key, *planted)
+        rt.rt_tune_cache_forget()
+        assert len(json.load(open(tmp_path / "tune.json"))["entries"]) == 1
+        b, outs = make_batch(rt, wls, handles, True)
+        try:
+            assert rt.rt_batch_shape(b) == planted
+            rt.rt_batch_launch(b)
+            torch.cuda.synchronize()
+            for i, (o, r) in enumerate(zip(outs, ref)):
+                assert torch.equal(o.cpu(), r), i
+        finally:
+            rt.rt_batch_destroy(b)
+    finally:
+        rt.rt_tune_cache_forget()
+        for h in handles:
+            h.close()
+
+
 def test_batch_image_matches_oracle(rt, oracle_mod):
     wls = small_batch()
     handles = [rt.SceneHandle(w.scene) for w in wls]
