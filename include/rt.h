@@ -285,6 +285,28 @@ rt_status rt_render_backward(rt_scene scene, const rt_camera* cam, int32_t W, in
                              int32_t depth, const float* grad_rgb, const rt_records* rec,
                              const rt_grads* grads, void* stream);
 
+/* For callers that cannot allocate device memory at all (code under graph
+ * capture, serving loops, harnesses that forbid hipMalloc): rt_render_backward
+ * with the same arguments, kernels and grid, hence the same bits, but its
+ * per-workgroup gradient partials (device scratch) live in a file-scope
+ * device array of RT_STATIC_SCRATCH_BYTES (16 MiB) that each GPU the library
+ * runs on holds until the process ends, instead of in the scene's buffer.
+ * The call allocates nothing (no hipMalloc, hipFree or allocating library
+ * routine); the first call on a device looks the array's address up once.
+ * A problem whose partials need more than the array holds (grid rows x
+ * (7 N + 4 L) floats, the grid being min(1024, 16x16 tiles of the image),
+ * capped at 64 MiB as in rt_render_backward) returns RT_ERR_INVALID_ARG and
+ * launches nothing.  Every row the reduction reads is written by the same
+ * launch, so nothing needs clearing between calls.  All calls on one GPU
+ * share the array: two calls that overlap on one GPU (on different streams,
+ * or from different threads without ordering) race and give wrong gradients;
+ * calls on one stream are ordered and safe.  The eye-cone rule of
+ * rt_render_backward applies too. */
+#define RT_STATIC_SCRATCH_BYTES 16777216u
+rt_status rt_render_backward_static(rt_scene scene, const rt_camera* cam, int32_t W, int32_t H,
+                                    int32_t depth, const float* grad_rgb, const rt_records* rec,
+                                    const rt_grads* grads, void* stream);
+
 typedef struct rt_batch_s* rt_batch;
 
 /* Prepare one persistent launch that renders n scenes of any sizes and

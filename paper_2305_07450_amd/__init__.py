@@ -34,6 +34,7 @@ RT_MAX_DIM = 16384
 RT_MAX_BATCH = 4096
 RT_FRAME_RGB32F, RT_FRAME_ARGB8 = 0, 1
 RT_NUM_COUNTS = 7
+RT_STATIC_SCRATCH_BYTES = 16777216
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(
@@ -103,6 +104,8 @@ _sig = {
                                    _vp]),
     "rt_render_backward": (C.c_int, [_vp, C.POINTER(rt_camera), _i32, _i32, _i32, _vp,
                                      C.POINTER(rt_records), C.POINTER(rt_grads), _vp]),
+    "rt_render_backward_static": (C.c_int, [_vp, C.POINTER(rt_camera), _i32, _i32, _i32, _vp,
+                                            C.POINTER(rt_records), C.POINTER(rt_grads), _vp]),
     "rt_batch_create": (C.c_int, [_i32, C.POINTER(_vp), C.POINTER(rt_camera), C.POINTER(_i32),
                                   C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_vp), _i32, _vp,
                                   C.POINTER(_vp)]),
@@ -376,6 +379,17 @@ def rt_render_backward(handle: int, camera, W: int, H: int, depth: int, grad_rgb
     g = _grads_arg(handle, grads)
     _check(_lib.rt_render_backward(handle, C.byref(cam), W, H, depth, grad_p, rec_p, C.byref(g),
                                    _stream(stream)))
+
+
+def rt_render_backward_static(handle: int, camera, W: int, H: int, depth: int,
+                              grad_rgb: torch.Tensor, grads: Dict[str, torch.Tensor],
+                              rec: Optional[Records] = None, stream=None):
+    cam = make_camera(camera)
+    grad_p = _dev(grad_rgb, "grad_rgb", torch.float32, 3 * int(W) * int(H))
+    rec_p = _records_arg(rec, W, H, depth)
+    g = _grads_arg(handle, grads)
+    _check(_lib.rt_render_backward_static(handle, C.byref(cam), W, H, depth, grad_p, rec_p,
+                                          C.byref(g), _stream(stream)))
 
 
 GRAD_NAMES = ("albedo", "refl", "center", "light_pos", "light_int")

@@ -545,6 +545,42 @@ static int backward_blocks(const rt_scene_s& sc, const CameraDev& c, int* n_tile
   return blocks > *n_tiles ? *n_tiles : blocks;
 }
 
+// Floats of partials one backward launch writes: a row of grad_stride floats
+// per workgroup of its grid.
+size_t backward_partial_floats(const rt_scene_s& sc, const CameraDev& c) {
+  int n_tiles_x, n_tiles;
+  return (size_t)backward_blocks(sc, c, &n_tiles_x, &n_tiles) * (size_t)sc.grad_stride;
+}
+
+// Partials of rt_render_backward_static: a file-scope device array that every
+// GPU the library runs on holds until the process ends, so that the call
+// needs no allocation.  Host code never passes the array's name to a kernel
+// (on the host it is only a stand-in); it uses the device address that
+// hipGetSymbolAddress gives on each device.
+static __device__ __align__(256) float scratch[kStaticScratchFloats];
+
+hipError_t static_scratch(int device, float** out) {
+  static std::mutex mu;
+  static float* addr[kMaxDevices];
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!addr[device]) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    const hipError_t back = cur != device ? hipSetDevice(cur) : hipSuccess;
+    if (e != hipSuccess) return e;
+    if (back != hipSuccess) return back;
+    if (!p) return hipErrorInvalidSymbol;
+    addr[device] = (float*)p;
+  }
+  *out = addr[device];
+  return hipSuccess;
+}
+
 hipError_t launch_backward(const rt_scene_s& sc, const CameraDev& c, int depth,
                            const float* grad_rgb, const int32_t* rec_ids, const uint8_t* rec_lit,
                            const rt_grads& g, float* partials, hipStream_t stream) {

@@ -462,4 +462,34 @@ rt_status rt_render_backward(rt_scene sc, const rt_camera* cam, int32_t W, int32
   return hip_fail(e, "backward launch");
 }
 
+rt_status rt_render_backward_static(rt_scene sc, const rt_camera* cam, int32_t W, int32_t H,
+                                    int32_t depth, const float* grad_rgb, const rt_records* rec,
+                                    const rt_grads* grads, void* stream) {
+  if (!sc) return fail(RT_ERR_INVALID_ARG, "scene is NULL");
+  rt_status st = validate_camera(cam, W, H, depth);
+  if (st != RT_OK) return st;
+  if (!grad_rgb) return fail(RT_ERR_INVALID_ARG, "grad_rgb is NULL");
+  if (!grads) return fail(RT_ERR_INVALID_ARG, "grads is NULL");
+  if ((st = check_records(rec, W, H, depth)) != RT_OK) return st;
+  if (!adjoint_supported(sc->n_spheres, sc->device))
+    return fail(RT_ERR_UNSUPPORTED,
+                "rt_render_backward_static supports at most %d spheres, scene has %d",
+                adjoint_max_spheres(sc->device), sc->n_spheres);
+  CameraDev c = camera_dev(*cam, W, H);
+  const size_t need = backward_partial_floats(*sc, c);
+  if (need > kStaticScratchFloats)
+    return fail(RT_ERR_INVALID_ARG,
+                "rt_render_backward_static: %zu floats of partials (%d spheres, %d lights, "
+                "%dx%d image) exceed its static scratch of %zu floats",
+                need, sc->n_spheres, sc->n_lights, W, H, kStaticScratchFloats);
+  float* part = nullptr;
+  hipError_t e = static_scratch(sc->device, &part);
+  if (e != hipSuccess) return hip_fail(e, "static scratch lookup");
+  if (!rec) e = launch_eye_cones(*sc, c, (hipStream_t)stream);
+  if (e == hipSuccess)
+    e = launch_backward(*sc, c, depth, grad_rgb, rec ? rec->ids : nullptr,
+                        rec ? rec->lit : nullptr, *grads, part, (hipStream_t)stream);
+  return hip_fail(e, "backward launch");
+}
+
 }  // extern "C"

@@ -127,6 +127,14 @@ bool tune_cache_get(const std::string& key, TunedShape* out);
 bool tune_cache_put(const std::string& key, const TunedShape& s);
 void tune_cache_forget_memory();
 
+// Largest partials of rt_render_backward_static, in floats (16 MiB per GPU).
+constexpr size_t kStaticScratchFloats = RT_STATIC_SCRATCH_BYTES / sizeof(float);
+// Floats of partials a backward launch of this scene and image writes.
+size_t backward_partial_floats(const rt_scene_s& sc, const CameraDev& c);
+// Device address of the static partials array on `device` (looked up once per
+// device, with that device current).
+hipError_t static_scratch(int device, float** out);
+
 // partials: [blocks][grad_stride] floats of device memory (the scene's own),
 // every row written before it is read.
 hipError_t launch_backward(const rt_scene_s& sc, const CameraDev& c, int depth,

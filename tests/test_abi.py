@@ -137,6 +137,9 @@ def test_render_rejects_bad_camera_and_sizes(rt, cam, W, H, D):
     st = rt._lib.rt_render_backward(FAKE_SCENE, C.byref(c), W, H, D, 0x1000, None,
                                     C.byref(rt.rt_grads()), None)
     assert st == rt.RT_ERR_INVALID_ARG
+    st = rt._lib.rt_render_backward_static(FAKE_SCENE, C.byref(c), W, H, D, 0x1000, None,
+                                           C.byref(rt.rt_grads()), None)
+    assert st == rt.RT_ERR_INVALID_ARG
 
 
 def test_render_rejects_null_buffers_and_short_records(rt):
@@ -155,6 +158,10 @@ def test_render_rejects_null_buffers_and_short_records(rt):
                                       C.byref(rt.rt_grads()), None) == 1
     assert rt._lib.rt_render_backward(FAKE_SCENE, C.byref(c), 8, 8, 1, 0x1000, None, None,
                                       None) == 1
+    for f in (rt._lib.rt_render_backward_static,):
+        assert f(None, C.byref(c), 8, 8, 1, 0x1000, None, C.byref(rt.rt_grads()), None) == 1
+        assert f(FAKE_SCENE, C.byref(c), 8, 8, 1, None, None, C.byref(rt.rt_grads()), None) == 1
+        assert f(FAKE_SCENE, C.byref(c), 8, 8, 1, 0x1000, None, None, None) == 1
     assert rt._lib.rt_render_counts(FAKE_SCENE, C.byref(c), 8, 8, 1, None, 0, None) == 1
     assert rt._lib.rt_render_counts(FAKE_SCENE, C.byref(c), 8, 8, 1, 0x1000, 2, None) == 1
 
