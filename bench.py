@@ -8,8 +8,11 @@ closest hits, shading with shadow rays and the mirror bounces of every
 pixel).  The scene is resident in HBM before timing starts; the image stays
 in HBM.
 
+The timed region is exactly --steps rt_render calls with nothing between
+them; ms_per_step is the larger of its HIP-event and host wall-clock means.
 Prints one JSON line: primary Mrays/s (value), fps, total Mrays/s, the frame
-time distribution (mean, median, the paper's mean of 10 consecutive frames),
+time distribution (mean, median, the paper's mean of 10 consecutive frames,
+from a second loop with one event between frames),
 the FP32 ALU roofline of the render kernel from the exact tests it executes,
 the brute-force variant (no culling) with its own fraction, the batched and
 forward+backward workloads, and the FP64 CPU oracle timed on the host beside
@@ -144,32 +147,62 @@ def time_gpu(fn, steps, warmup, stream):
     return e0.elapsed_time(e1) / steps
 
 
+def time_steps(step, steps, warmup, stream):
+    """The timed region: exactly `steps` calls of step(), after `warmup`,
+    bracketed by a synchronize and one HIP event on `stream` on each side,
+    with nothing issued between the calls.  Returns (GPU ms per step, host
+    wall ms per step)."""
+    import torch
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3
+    return e0.elapsed_time(e1) / steps, wall / steps
+
+
+def time_frames(step, steps, warmup, stream):
+    """Per-frame GPU times: one HIP event between consecutive calls of step()
+    (steps + 1 events in all), for the distribution of frame times."""
+    import torch
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    es = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    es[0].record(stream)
+    for k in range(steps):
+        step()
+        es[k + 1].record(stream)
+    torch.cuda.synchronize()
+    return [es[k].elapsed_time(es[k + 1]) for k in range(steps)]
+
+
 def time_split(prep, kern, steps, warmup, stream):
-    """Per-call HIP-event times of kern() alone and of prep() + kern() (one
-    step), on `stream`, over `steps` calls after `warmup`; and the host wall
-    clock of the whole loop.  Returns (kernel ms list, step ms list, wall ms)."""
+    """Per-launch HIP-event times of kern() alone, issued after prep() on
+    `stream`: events right before and after each kern() launch, over `steps`
+    calls after `warmup`.  Returns the kernel ms list."""
     import torch
     for _ in range(warmup):
         prep()
         kern()
     torch.cuda.synchronize()
     ev = lambda: torch.cuda.Event(enable_timing=True)
-    es = [ev() for _ in range(steps + 1)]
     ks = [ev() for _ in range(steps)]
     ke = [ev() for _ in range(steps)]
-    t0 = time.perf_counter()
     for k in range(steps):
-        es[k].record(stream)
         prep()
         ks[k].record(stream)
         kern()
         ke[k].record(stream)
-    es[steps].record(stream)
     torch.cuda.synchronize()
-    wall = (time.perf_counter() - t0) * 1e3
-    kernel = [ks[k].elapsed_time(ke[k]) for k in range(steps)]
-    step = [es[k].elapsed_time(es[k + 1]) for k in range(steps)]
-    return kernel, step, wall
+    return [ks[k].elapsed_time(ke[k]) for k in range(steps)]
 
 
 def dist(ms):
@@ -442,14 +475,18 @@ def main():
     counts_bf = rt.render_counts(h.handle, wl.camera, W, H, D, flags=rt.RT_RENDER_NO_PREFILTER)
     stream = torch.cuda.current_stream()
     ready = rt.RT_RENDER_CONES_READY
-    # one step = rt_render's two launches, issued apart so that the render
-    # kernel gets events of its own: the eye cones, then the render
+    # one step = one rt_render: the eye-cone launch, then the render kernel
+    step = lambda: rt.rt_render(h.handle, wl.camera, W, H, D, rgb, None, None, stream)
+    torch.cuda.synchronize()
+    ms_step_gpu, ms_step_wall = time_steps(step, args.steps, args.warmup, stream)
+    ms_step = max(ms_step_wall, ms_step_gpu)
+    # outside the timed region: per-frame times (one event between frames),
+    # and the render kernel alone, its two launches issued apart so that it
+    # gets events of its own
+    step_ms = time_frames(step, args.steps, 10, stream)
     prep = lambda: rt.rt_render_prepare(h.handle, wl.camera, stream)
     kern = lambda: rt.rt_render_ex(h.handle, wl.camera, W, H, D, rgb, None, None, ready, stream)
-    torch.cuda.synchronize()
-    kernel_ms, step_ms, wall = time_split(prep, kern, args.steps, args.warmup, stream)
-    ms_step_gpu = sum(step_ms) / args.steps
-    ms_step = max(wall / args.steps, ms_step_gpu)
+    kernel_ms = time_split(prep, kern, args.steps, 10, stream)
     ms_kernel = sum(kernel_ms) / args.steps
     assert torch.isfinite(rgb).all()
     ids = torch.empty((H, W), dtype=torch.int32, device=dev)
@@ -475,6 +512,7 @@ def main():
                    "seed": scenegen.canonical_seed(args.workload), "parallelism": "single-gpu"},
         "fps": round(1e3 / ms_step, 2),
         "total_mrays_per_s": round(rays / (ms_step * 1e-3) / 1e6, 2),
+        "step_ms": {"gpu_events": round(ms_step_gpu, 5), "host_wall": round(ms_step_wall, 5)},
         "frame_ms": dist(step_ms),
         "render_kernel_ms": dist(kernel_ms),
         **{k: v for k, v in work_rates(counts, ms_step).items()
@@ -494,14 +532,17 @@ def main():
         # the method's brute force: the same image without the culling, whose
         # executed tests are exactly the method's algorithmic count
         flags = rt.RT_RENDER_NO_PREFILTER | ready
-        bf_kernel, bf_step, _ = time_split(
+        bf_kernel = time_split(
             prep, lambda: rt.rt_render_ex(h.handle, wl.camera, W, H, D, rgb, None, None, flags,
                                           stream), 20, 3, stream)
         ms_bf = sum(bf_kernel) / len(bf_kernel)
+        bf_step, _ = time_steps(
+            lambda: rt.rt_render_ex(h.handle, wl.camera, W, H, D, rgb, None, None,
+                                    rt.RT_RENDER_NO_PREFILTER, stream), 20, 3, stream)
         bf_flops = test_flops(counts_bf, True)
         out["brute_force"] = {
             "kernel": "render_kernel without cone tests and wave bounds (RT_RENDER_NO_PREFILTER)",
-            "kernel_ms": round(ms_bf, 5), "step_ms": round(sum(bf_step) / len(bf_step), 5),
+            "kernel_ms": round(ms_bf, 5), "step_ms": round(bf_step, 5),
             "flops_per_launch": bf_flops,
             "achieved": round(bf_flops / (ms_bf * 1e-3) / 1e12, 3),
             "frac": round(frac_of_peak(bf_flops, ms_bf), 4),
