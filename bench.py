@@ -3,10 +3,13 @@
 
 A step is one rt_render of the 1920x1080 workload (64 spheres + ground plane,
 2 point lights, reflection depth 4, one primary ray per pixel, seeded
-synthetic scene): the eye-cone launch, then the render kernel (primary rays,
-closest hits, shading with shadow rays and the mirror bounces of every
-pixel).  The scene is resident in HBM before timing starts; the image stays
-in HBM.
+synthetic scene): the preparation launch (eye cones, tile order), then the
+render kernel (primary rays, closest hits, shading with shadow rays and the
+mirror bounces of every pixel).  The scene is resident in HBM before timing
+starts; the image stays in HBM.  The render takes its tiles longest first by
+the durations the previous render of the scene at this size measured; the
+JSON also gives the row-order loop, the first render of a fresh upload and a
+turning camera.
 
 The timed region is exactly --steps rt_render calls with nothing between
 them; ms_per_step is the larger of its HIP-event and host wall-clock means.
@@ -203,6 +206,26 @@ def time_split(prep, kern, steps, warmup, stream):
         ke[k].record(stream)
     torch.cuda.synchronize()
     return [ks[k].elapsed_time(ke[k]) for k in range(steps)]
+
+
+def first_render_ms(rt, wl, rgb, stream, uploads=3):
+    """The first rt_render of freshly uploaded copies of the scene (no
+    recorded tile durations yet: row order), HIP events around the one call;
+    the median over `uploads` uploads."""
+    import statistics
+    import torch
+    out = []
+    for _ in range(uploads):
+        with rt.SceneHandle(wl.scene) as h:
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            rt.rt_render(h.handle, wl.camera, wl.W, wl.H, wl.depth, rgb, None, None, stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            out.append(e0.elapsed_time(e1))
+    return round(statistics.median(out), 5)
 
 
 def dist(ms):
@@ -484,11 +507,34 @@ def main():
     # and the render kernel alone, its two launches issued apart so that it
     # gets events of its own
     step_ms = time_frames(step, args.steps, 10, stream)
-    prep = lambda: rt.rt_render_prepare(h.handle, wl.camera, stream)
+    prep = lambda: rt.rt_render_prepare(h.handle, wl.camera, W, H, stream)
     kern = lambda: rt.rt_render_ex(h.handle, wl.camera, W, H, D, rgb, None, None, ready, stream)
     kernel_ms = time_split(prep, kern, args.steps, 10, stream)
     ms_kernel = sum(kernel_ms) / args.steps
     assert torch.isfinite(rgb).all()
+    # the tile schedule (tiles longest first, by the durations the previous
+    # render of the scene at this size measured): the same loop in row order,
+    # the first render of a freshly uploaded scene (row order, recording), and
+    # a camera that turns 0.05 degrees a frame (each order measured on the
+    # previous, different view)
+    row = lambda: rt.rt_render_ex(h.handle, wl.camera, W, H, D, rgb, None, None,
+                                  rt.RT_RENDER_ROW_ORDER, stream)
+    row_gpu, row_wall = time_steps(row, args.steps, 10, stream)
+    yaws = [0.05 * i for i in range(50)] + [0.05 * (50 - i) for i in range(50)]
+    cams = [scenegen.Camera(yaw_deg=y) for y in yaws]
+    turn = [0]
+
+    def moving():
+        turn[0] += 1
+        rt.rt_render(h.handle, cams[turn[0] % len(cams)], W, H, D, rgb, None, None, stream)
+    mov_gpu, mov_wall = time_steps(moving, args.steps, 10, stream)
+    schedule = {
+        "order": "tiles longest first, by the durations the previous render of the scene at "
+                 "this size measured; the first render of a size takes row order",
+        "row_order_ms_per_step": round(max(row_gpu, row_wall), 5),
+        "first_render_ms": first_render_ms(rt, wl, rgb, stream),
+        "moving_camera_ms_per_step": round(max(mov_gpu, mov_wall), 5),
+        "moving_camera": "yaw 0 to 2.45 degrees and back in steps of 0.05 degrees, one a frame"}
     ids = torch.empty((H, W), dtype=torch.int32, device=dev)
     rt.rt_render(h.handle, wl.camera, W, H, D, rgb, ids, None, stream)
     torch.cuda.synchronize()
@@ -513,6 +559,7 @@ def main():
         "fps": round(1e3 / ms_step, 2),
         "total_mrays_per_s": round(rays / (ms_step * 1e-3) / 1e6, 2),
         "step_ms": {"gpu_events": round(ms_step_gpu, 5), "host_wall": round(ms_step_wall, 5)},
+        "tile_schedule": schedule,
         "frame_ms": dist(step_ms),
         "render_kernel_ms": dist(kernel_ms),
         **{k: v for k, v in work_rates(counts, ms_step).items()

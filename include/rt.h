@@ -175,13 +175,22 @@ int64_t rt_records_bytes(int32_t W, int32_t H, int32_t depth);
  *   rgb_out  device float32 [H][W][3], linear colour, not clamped;
  *   id_out   device int32 [H][W] primary hit id (-1 = miss), or NULL;
  *   rec      records for rt_render_backward, or NULL.
- * Launches two kernels: the cones of the spheres seen from the camera's eye,
- * written into the scene's own buffer, then the render.  No allocation,
- * capture-safe.  Because the eye-cone table lives in the scene, calls that
- * write it (rt_render, rt_render_ex, rt_render_soft, rt_render_counts and
- * rt_render_backward with rec == NULL) must not overlap in time for one
- * scene: on one stream they are ordered; on different streams the caller
- * orders them (events), or a render may read another call's cones. */
+ * Launches two kernels: the preparation, then the render.  The preparation
+ * writes the cones of the spheres seen from the camera's eye into the
+ * scene's own buffer.  For images of 4096 to 131072 8x8 tiles the render
+ * also records how long each of its tiles took (a byte per tile and a count
+ * per duration bin, in the scene's buffer), and the preparation of the next
+ * render of the scene at the same size turns that record into the order in
+ * which the render takes its tiles: longest first (the first render of a
+ * size takes row order).  The order changes no pixel, only how well the
+ * tiles fill the GPU; a record from another view or before rt_scene_update
+ * is still used, as a guess.  No allocation, capture-safe.  Because the
+ * eye-cone, record and order tables live in the scene, calls that write them
+ * (rt_render, rt_render_ex, rt_render_prepare, rt_render_soft,
+ * rt_render_counts and rt_render_backward with rec == NULL) must not overlap
+ * in time for one scene: on one stream they are ordered; on different
+ * streams the caller orders them (events), or a render may read another
+ * call's tables. */
 rt_status rt_render(rt_scene scene, const rt_camera* cam, int32_t W, int32_t H, int32_t depth,
                     float* rgb_out, int32_t* id_out, const rt_records* rec, void* stream);
 
@@ -194,15 +203,21 @@ rt_status rt_render(rt_scene scene, const rt_camera* cam, int32_t W, int32_t H, 
                                       either way; this flag exists to check
                                       that */
 
-#define RT_RENDER_CONES_READY 2u   /* rt_render_ex only: skip the eye-cone
-                                      launch; the caller has called
-                                      rt_render_prepare with a camera at the
-                                      same eye position, on the same stream,
-                                      after the last call that rewrote the
-                                      scene's cones (any render, count or
-                                      re-traced backward of the scene, or a
-                                      scene update).  Stale cones give a wrong
-                                      image, never an out-of-bounds access */
+#define RT_RENDER_CONES_READY 2u   /* rt_render_ex only: skip the
+                                      preparation launch; the caller has
+                                      called rt_render_prepare with a camera
+                                      at the same eye position, on the same
+                                      stream, after the last call that
+                                      rewrote the scene's cones (any render,
+                                      count or re-traced backward of the
+                                      scene, or a scene update).  Stale cones
+                                      give a wrong image, never an
+                                      out-of-bounds access; the tile order of
+                                      that preparation is used only if it was
+                                      made for the same W x H */
+#define RT_RENDER_ROW_ORDER 4u     /* rt_render_ex only: take the tiles in
+                                      row order and record no durations; the
+                                      same image bits */
 
 /* rt_render with flags (0 = rt_render); the same two launches (one with
  * RT_RENDER_CONES_READY) and the same rule for calls on one scene. */
@@ -211,12 +226,15 @@ rt_status rt_render_ex(rt_scene scene, const rt_camera* cam, int32_t W, int32_t 
                        void* stream);
 
 /* The first of rt_render's two launches on its own: the cones of the scene's
- * spheres seen from the camera's eye, written into the scene's buffer, for a
- * following rt_render_ex with RT_RENDER_CONES_READY (so that the render
- * kernel can be timed or captured on its own).  Only the eye position and
- * the camera's validity matter.  One launch, no allocation, capture-safe; the
- * same overlap rule as rt_render. */
-rt_status rt_render_prepare(rt_scene scene, const rt_camera* cam, void* stream);
+ * spheres seen from the camera's eye and, where rt_render orders its tiles,
+ * the tile order of a W x H image from the last recorded render of that
+ * size, written into the scene's buffer, for a following rt_render_ex with
+ * RT_RENDER_CONES_READY (so that the render kernel can be timed or captured
+ * on its own; the first such render after it records its tile durations).
+ * One launch, no allocation, capture-safe; the same overlap rule as
+ * rt_render. */
+rt_status rt_render_prepare(rt_scene scene, const rt_camera* cam, int32_t W, int32_t H,
+                            void* stream);
 
 /* Render one image with soft shadows (the paper's soft cast shadows, Section
  * 3.6.1): every light is a sphere of radius light_radius about its position,

@@ -28,6 +28,7 @@ RT_MAX_SPHERES = 4096
 RT_MAX_PLANES = 16
 RT_RENDER_NO_PREFILTER = 1
 RT_RENDER_CONES_READY = 2
+RT_RENDER_ROW_ORDER = 4
 RT_MAX_SAMPLES = 4096
 RT_MAX_SKY_DIM = 16384
 RT_MAX_DIM = 16384
@@ -97,7 +98,7 @@ _sig = {
                             C.POINTER(rt_records), _vp]),
     "rt_render_ex": (C.c_int, [_vp, C.POINTER(rt_camera), _i32, _i32, _i32, _vp, _vp,
                                C.POINTER(rt_records), C.c_uint32, _vp]),
-    "rt_render_prepare": (C.c_int, [_vp, C.POINTER(rt_camera), _vp]),
+    "rt_render_prepare": (C.c_int, [_vp, C.POINTER(rt_camera), C.c_int32, C.c_int32, _vp]),
     "rt_render_soft": (C.c_int, [_vp, C.POINTER(rt_camera), _i32, _i32, _i32, _i32, C.c_float,
                                  _vp, _vp, C.c_uint32, _vp]),
     "rt_render_counts": (C.c_int, [_vp, C.POINTER(rt_camera), _i32, _i32, _i32, _vp, C.c_uint32,
@@ -332,10 +333,11 @@ def rt_render_ex(handle: int, camera, W: int, H: int, depth: int, rgb_out: torch
 
 
 # algorithmic tests, rays, then the tests the kernel executes (include/rt.h)
-def rt_render_prepare(handle: int, camera, stream=None):
-    """The eye-cone launch of rt_render on its own (see RT_RENDER_CONES_READY)."""
+def rt_render_prepare(handle: int, camera, W: int, H: int, stream=None):
+    """The preparation launch of rt_render on its own: eye cones and the tile
+    order of a W x H image (see RT_RENDER_CONES_READY)."""
     cam = make_camera(camera)
-    _check(_lib.rt_render_prepare(handle, C.byref(cam), _stream(stream)))
+    _check(_lib.rt_render_prepare(handle, C.byref(cam), int(W), int(H), _stream(stream)))
 
 
 COUNT_NAMES = ("sphere_tests", "plane_tests", "primary_rays", "reflection_rays", "shadow_rays",

@@ -27,6 +27,31 @@ struct RecordSink {
   __device__ __forceinline__ void lit(int k, uint32_t m) { lit_plane[k * plane + pix] = (uint8_t)m; }
 };
 
+// Tile of this workgroup: blockIdx in row order, or the scene's order table.
+__device__ __forceinline__ int tile_of(const SceneDev& s) {
+  const int n = (int)(gridDim.x * gridDim.y);
+  const int b = blockIdx.y * gridDim.x + blockIdx.x;
+  if (!(s.sched_mode & kSchedOrdered)) return b;
+  return min(max(((const RT_CONSTANT int*)(s.sched + kSchedOrder))[b], 0), n - 1);
+}
+
+// The tile's duration for the next render's order: core clocks since t_start,
+// as bin floor(3 log2(clocks)) - 36 clamped to [0, kSchedBins) (a third of an
+// octave each, 4096 to about 200 000 clocks): one byte per tile, and one to
+// the histogram of its chunk of kSchedHistChunk tiles (one atomic per tile, a
+// cache line of counts per chunk, issued as the tiles finish).
+__device__ __forceinline__ void record_duration(const SceneDev& s, int t, uint64_t t_start) {
+  const float clocks = (float)(__builtin_amdgcn_s_memtime() - t_start);
+  const int bin = min(max((int)(3.0f * __builtin_amdgcn_logf(fmaxf(clocks, 1.0f))) - 36, 0),
+                      kSchedBins - 1);
+  if (__lane_id() == 0) {
+    s.sched[kSchedBin + t] = (uint8_t)bin;
+    uint32_t* hist = (uint32_t*)(s.sched + kSchedHist) +
+                     ((s.sched_mode & kSchedHistSet1) ? kSchedChunks * kSchedBins : 0);
+    atomicAdd(hist + (t / kSchedHistChunk) * kSchedBins + bin, 1u);
+  }
+}
+
 template <bool kRecords, bool kPrefilter, class Bg>
 __global__ __launch_bounds__(kRenderThreads) void render_kernel(SceneDev s, CameraDev c, int depth,
                                                       float* __restrict__ rgb,
@@ -34,8 +59,16 @@ __global__ __launch_bounds__(kRenderThreads) void render_kernel(SceneDev s, Came
                                                       int32_t* __restrict__ rec_ids,
                                                       uint8_t* __restrict__ rec_lit) {
   const int lane = threadIdx.x;
-  const int x = blockIdx.x * kTile + (lane & 7);
-  const int y = blockIdx.y * kTile + (lane >> 3);
+  // the tile of this workgroup: in row order, or the b-th of the scene's
+  // order (longest first, from the durations the last render recorded)
+  const int t = tile_of(s);
+  const int ty = t / (int)gridDim.x;
+  const int tx = t - ty * (int)gridDim.x;
+  // the start time waits in LDS, not in registers, until the tile is done
+  __shared__ uint64_t s_start;
+  if (s.sched_mode & kSchedRecord) s_start = __builtin_amdgcn_s_memtime();
+  const int x = tx * kTile + (lane & 7);
+  const int y = ty * kTile + (lane >> 3);
   // lanes outside the image run along (clamped pixel, no output) so that the
   // whole wave executes the path code together; a wave with no pixel leaves
   const bool live = x < c.W && y < c.H;
@@ -65,6 +98,7 @@ __global__ __launch_bounds__(kRenderThreads) void render_kernel(SceneDev s, Came
     rgb[3 * pix + 2] = cb;
     if (id_out) id_out[pix] = prim;
   }
+  if (s.sched_mode & kSchedRecord) record_duration(s, tile_of(s), s_start);
 }
 
 // Soft-shadow render: the same paths with every light sampled (SoftShadows).

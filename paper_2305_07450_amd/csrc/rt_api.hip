@@ -246,6 +246,7 @@ rt_status rt_scene_upload(const rt_scene_desc* d, void* stream, rt_scene* out) {
   size_t o_part = take((size_t)blocks * sc->grad_stride * sizeof(float));
   static_assert(RT_MAX_SAMPLES % 8 == 0, "soft sample table is read in blocks of 8");
   size_t o_soft = take((size_t)RT_MAX_SAMPLES * sizeof(float2));
+  size_t o_sched = take(kSchedBytes);
   sc->bytes = off;
   hipError_t e = hipGetDevice(&sc->device);
   if (e == hipSuccess) e = hipMalloc(&sc->buffer, sc->bytes);
@@ -265,6 +266,13 @@ rt_status rt_scene_upload(const rt_scene_desc* d, void* stream, rt_scene* out) {
   sc->staging = (float*)(base + o_stage);
   sc->partials = (float*)(base + o_part);
   sc->soft_table = (float2*)(base + o_soft);
+  sc->sched = (uint8_t*)(base + o_sched);
+  e = hipMemsetAsync(sc->sched + kSchedHist, 0, kSchedBytes - kSchedHist, (hipStream_t)stream);
+  if (e != hipSuccess) {
+    (void)hipFree(sc->buffer);
+    delete sc;
+    return hip_fail(e, "scene initialisation");
+  }
   st = upload_values(sc, d, (hipStream_t)stream);
   if (st != RT_OK) {
     (void)hipFree(sc->buffer);
@@ -374,32 +382,66 @@ rt_status rt_render(rt_scene sc, const rt_camera* cam, int32_t W, int32_t H, int
   return rt_render_ex(sc, cam, W, H, depth, rgb_out, id_out, rec, 0, stream);
 }
 
-rt_status rt_render_prepare(rt_scene sc, const rt_camera* cam, void* stream) {
+// The launch before a hard-shadow render: eye cones and, where scheduling
+// applies, the tile order from the durations the last render of this size
+// recorded (remembered for RT_RENDER_CONES_READY renders of the same size).
+static hipError_t prepare_render(rt_scene_s* sc, const CameraDev& c, bool row_order,
+                                 hipStream_t stream) {
+  const bool sched = !row_order && schedule_applies(*sc, c.W, c.H);
+  bool ordered = false;
+  hipError_t e = launch_prepare(*sc, c, sched, &ordered, stream);
+  sc->order_W = (e == hipSuccess && ordered) ? c.W : 0;
+  sc->order_H = (e == hipSuccess && ordered) ? c.H : 0;
+  sc->rec_W = (e == hipSuccess && sched) ? c.W : 0;
+  sc->rec_H = (e == hipSuccess && sched) ? c.H : 0;
+  return e;
+}
+
+rt_status rt_render_prepare(rt_scene sc, const rt_camera* cam, int32_t W, int32_t H,
+                            void* stream) {
   if (!sc) return fail(RT_ERR_INVALID_ARG, "scene is NULL");
-  // the eye cones depend on the eye position only; any valid size will do
-  rt_status st = validate_camera(cam, 1, 1, 0);
+  rt_status st = validate_camera(cam, W, H, 0);
   if (st != RT_OK) return st;
-  return hip_fail(launch_eye_cones(*sc, camera_dev(*cam, 1, 1), (hipStream_t)stream),
-                  "eye-cone launch");
+  return hip_fail(prepare_render(sc, camera_dev(*cam, W, H), false, (hipStream_t)stream),
+                  "prepare launch");
 }
 
 rt_status rt_render_ex(rt_scene sc, const rt_camera* cam, int32_t W, int32_t H, int32_t depth,
                        float* rgb_out, int32_t* id_out, const rt_records* rec, uint32_t flags,
                        void* stream) {
   if (!sc) return fail(RT_ERR_INVALID_ARG, "scene is NULL");
-  if (flags & ~(uint32_t)(RT_RENDER_NO_PREFILTER | RT_RENDER_CONES_READY))
+  if (flags & ~(uint32_t)(RT_RENDER_NO_PREFILTER | RT_RENDER_CONES_READY | RT_RENDER_ROW_ORDER))
     return fail(RT_ERR_INVALID_ARG, "unknown render flags 0x%x", flags);
   rt_status st = validate_camera(cam, W, H, depth);
   if (st != RT_OK) return st;
   if (!rgb_out) return fail(RT_ERR_INVALID_ARG, "rgb_out is NULL");
   if ((st = check_records(rec, W, H, depth)) != RT_OK) return st;
   CameraDev c = camera_dev(*cam, W, H);
-  hipError_t e = (flags & RT_RENDER_CONES_READY) ? hipSuccess
-                                                 : launch_eye_cones(*sc, c, (hipStream_t)stream);
+  const bool row_order = flags & RT_RENDER_ROW_ORDER;
+  hipError_t e = (flags & RT_RENDER_CONES_READY)
+                     ? hipSuccess
+                     : prepare_render(sc, c, row_order, (hipStream_t)stream);
+  SceneDev s = sc->view();
+  // the brute-force variant keeps row order and records nothing
+  const bool sched =
+      !row_order && !(flags & RT_RENDER_NO_PREFILTER) && schedule_applies(*sc, W, H);
+  // the order of the last prepare, if it was made for this image size
+  if (sched && sc->order_W == W && sc->order_H == H) s.sched_mode |= kSchedOrdered;
+  // every tile records its duration for the next render of this size, into
+  // the histogram set the last prepare zeroed (if it prepared this size and
+  // no render has recorded since)
+  const bool record = sched && sc->rec_W == W && sc->rec_H == H;
+  if (record) s.sched_mode |= kSchedRecord | (sc->hist_set ? 0 : kSchedHistSet1);
   if (e == hipSuccess)
-    e = launch_render(sc->view(), c, depth, rgb_out, id_out, rec ? rec->ids : nullptr,
+    e = launch_render(s, c, depth, rgb_out, id_out, rec ? rec->ids : nullptr,
                       rec ? rec->lit : nullptr, !(flags & RT_RENDER_NO_PREFILTER),
                       (hipStream_t)stream);
+  if (e == hipSuccess && record) {
+    sc->hist_set ^= 1;   // the set just filled holds this render's record
+    sc->hist_W = W;
+    sc->hist_H = H;
+    sc->rec_W = sc->rec_H = 0;
+  }
   return hip_fail(e, "render launch");
 }
 

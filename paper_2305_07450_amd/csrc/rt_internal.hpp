@@ -34,6 +34,13 @@ struct rt_scene_s {
   int grad_stride = 0;          // 7N + 4L (padded)
   float4* sky = nullptr;        // own hipMalloc: [sky_h][sky_w] rgb + unused, or none
   int sky_w = 0, sky_h = 0;
+  // tile schedule of the hard-shadow render (schedule.hip): the area of
+  // kSchedBytes at `sched` (layout in trace.hpp)
+  uint8_t* sched = nullptr;
+  int hist_set = 0;                // histogram set holding the last record
+  int hist_W = 0, hist_H = 0;      // image of the recorded duration bins (0: none)
+  int order_W = 0, order_H = 0;    // image the last prepare ordered (0: none)
+  int rec_W = 0, rec_H = 0;        // image the next render may record (other set zeroed)
 
   rtk::SceneDev view() const {
     rtk::SceneDev s;
@@ -45,6 +52,8 @@ struct rt_scene_s {
     s.ambient = ambient; s.spec_strength = spec_strength; s.t_min = t_min;
     s.bg_r = bg[0]; s.bg_g = bg[1]; s.bg_b = bg[2];
     s.sky = sky; s.sky_w = sky_w; s.sky_h = sky_h;
+    s.sched = sched;
+    s.sched_mode = 0;
     return s;
   }
 };
@@ -57,6 +66,11 @@ constexpr int kRenderThreads = 64;
 inline dim3 render_grid(int W, int H) {
   return dim3((W + kRenderTile - 1) / kRenderTile, (H + kRenderTile - 1) / kRenderTile);
 }
+
+// Tile scheduling of the hard-shadow render (schedule.hip): images of at
+// least kSchedMinTiles tiles (fewer all start at once) and at most
+// kSchedMaxTiles (the scene's tables).
+constexpr int kSchedMinTiles = 4096;
 
 // Workgroups of the persistent adjoint grid (one partial-gradient slot each).
 constexpr int kAdjointBlocks = 1024;
@@ -86,6 +100,13 @@ hipError_t launch_sky_pack(const float* rgb, float4* sky, int texels, hipStream_
 
 // Cones of every sphere seen from the camera's eye, into sc.eye_cone.
 hipError_t launch_eye_cones(const rt_scene_s& sc, const CameraDev& c, hipStream_t stream);
+// The eye cones and, with `schedule` (only where schedule_applies), the
+// scene's tile order for a render of c.W x c.H from the durations the last
+// render of that size recorded (*ordered: an order was written), and the
+// zeroed histogram the following render records into.
+hipError_t launch_prepare(rt_scene_s& sc, const CameraDev& c, bool schedule, bool* ordered,
+                          hipStream_t stream);
+bool schedule_applies(const rt_scene_s& sc, int W, int H);
 hipError_t launch_render_soft(const rt_scene_s& sc, const CameraDev& c, int depth, int samples,
                               float radius, float* rgb, int32_t* ids, bool prefilter,
                               hipStream_t stream);

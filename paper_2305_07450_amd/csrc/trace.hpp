@@ -43,7 +43,27 @@ struct SceneDev {
   float bg_r, bg_g, bg_b;
   const float4* sky;     // [sky_h][sky_w] rgb, unused; NULL: plain background
   int sky_w, sky_h;
+  // tile schedule of the render (see render.hip): the scene's schedule area
+  // (kSchedOrder: int32 tile order; kSchedBin: uint8 duration bin per tile)
+  // and what to do with it
+  uint8_t* sched;
+  int sched_mode;   // kSchedOrdered | kSchedRecord | kSchedHistSet1
 };
+
+// Tile schedule of a render: durations recorded in kSchedBins bins of a third
+// of an octave each, for images of at most kSchedMaxTiles tiles; the layout
+// of a scene's schedule area (byte offsets) and the render's mode bits.
+constexpr int kSchedBins = 16;
+constexpr int kSchedMaxTiles = 1 << 17;
+constexpr int kSchedChunk = 1024;   // tiles per block of the preparation, per histogram
+constexpr int kSchedHistChunk = 256;   // tiles per histogram (one cache line of counts)
+constexpr int kSchedChunks = kSchedMaxTiles / kSchedHistChunk;
+constexpr size_t kSchedOrder = 0;                                      // int32 [tiles]
+constexpr size_t kSchedBin = kSchedOrder + 4 * (size_t)kSchedMaxTiles;     // uint8 [tiles]
+// uint32 [2][kSchedChunks][kSchedBins]: tiles of each histogram chunk per bin
+constexpr size_t kSchedHist = kSchedBin + (size_t)kSchedMaxTiles;
+constexpr size_t kSchedBytes = kSchedHist + 2 * 4 * (size_t)kSchedChunks * kSchedBins;
+constexpr int kSchedOrdered = 1, kSchedRecord = 2, kSchedHistSet1 = 4;
 
 // Sphere tables (geom, eye_cone, light_cone) hold n4 = round_up(N, kGroup)
 // entries plus one more group, so the loops below read kGroup spheres with

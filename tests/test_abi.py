@@ -313,11 +313,13 @@ def test_scene_counts_rejects_null(rt):
 
 def test_prepare_and_flags_are_checked_on_the_host(rt):
     c = rt.make_camera(Camera())
-    assert rt._lib.rt_render_prepare(None, C.byref(c), None) == rt.RT_ERR_INVALID_ARG
-    assert rt._lib.rt_render_prepare(FAKE_SCENE, None, None) == rt.RT_ERR_INVALID_ARG
+    assert rt._lib.rt_render_prepare(None, C.byref(c), 8, 8, None) == rt.RT_ERR_INVALID_ARG
+    assert rt._lib.rt_render_prepare(FAKE_SCENE, None, 8, 8, None) == rt.RT_ERR_INVALID_ARG
     bad = rt.make_camera(Camera(fov_deg=0.0))
-    assert rt._lib.rt_render_prepare(FAKE_SCENE, C.byref(bad), None) == rt.RT_ERR_INVALID_ARG
-    assert rt._lib.rt_render_ex(FAKE_SCENE, C.byref(c), 8, 8, 1, 0x1000, None, None, 4,
+    assert rt._lib.rt_render_prepare(FAKE_SCENE, C.byref(bad), 8, 8, None) == rt.RT_ERR_INVALID_ARG
+    for W, H in ((0, 8), (8, 0), (rt.RT_MAX_DIM + 1, 8)):
+        assert rt._lib.rt_render_prepare(FAKE_SCENE, C.byref(c), W, H, None) == rt.RT_ERR_INVALID_ARG
+    assert rt._lib.rt_render_ex(FAKE_SCENE, C.byref(c), 8, 8, 1, 0x1000, None, None, 8,
                                 None) == rt.RT_ERR_INVALID_ARG
     # soft renders and frames take no prepared cones
     assert rt._lib.rt_render_soft(FAKE_SCENE, C.byref(c), 8, 8, 1, 8, 0.5, 0x1000, None,

@@ -277,10 +277,106 @@ def test_prepared_cones_give_the_same_bits(rt, config):
         rt.rt_render(h.handle, wl.camera, W, H, D, a, ia)
         # another camera's cones in between, then the prepared render
         other = rt.render(h.handle, Camera(yaw_deg=40.0), W, H, D)
-        rt.rt_render_prepare(h.handle, wl.camera)
+        rt.rt_render_prepare(h.handle, wl.camera, W, H)
         b = torch.empty_like(a)
         ib = torch.empty_like(ia)
         rt.rt_render_ex(h.handle, wl.camera, W, H, D, b, ib, None, rt.RT_RENDER_CONES_READY)
         torch.cuda.synchronize()
         del other
+    assert torch.equal(a, b) and torch.equal(ia, ib)
+
+
+def _render_flags(rt, h, wl, flags, records=False, camera=None):
+    """One rt_render_ex into NaN-filled outputs, so that a tile the launch
+    skipped cannot pass for a rendered one."""
+    W, H, D = wl.W, wl.H, wl.depth
+    img = torch.full((H, W, 3), float("nan"), device="cuda")
+    ids = torch.full((H, W), -7, dtype=torch.int32, device="cuda")
+    rec = rt.Records(W, H, D) if records else None
+    rt.rt_render_ex(h.handle, camera or wl.camera, W, H, D, img, ids, rec, flags)
+    torch.cuda.synchronize()
+    return img, ids, rec
+
+
+@pytest.mark.parametrize("config", [1, 2, 4])
+def test_tile_order_changes_no_bits(rt, config):
+    """rt_render records every tile's duration and the next render of the
+    scene at that size takes the tiles longest first (1080p, 4K at 129 600
+    tiles near the order table's limit, 720p): image, ids and records equal
+    the row-order render bit for bit, render after render."""
+    wl = scenegen.make_workload(config)
+    log("case tile order", wl.name)
+    with rt.SceneHandle(wl.scene) as h:
+        want, iw, rw = _render_flags(rt, h, wl, rt.RT_RENDER_ROW_ORDER, records=True)
+        for k in range(3):   # row order and recording, then two ordered renders
+            a, ia, ra = _render_flags(rt, h, wl, 0, records=True)
+            assert torch.equal(a, want) and torch.equal(ia, iw), k
+            assert torch.equal(ra.ids, rw.ids) and torch.equal(ra.lit, rw.lit), k
+
+
+def test_tile_order_from_other_views_and_updates(rt):
+    """An order measured for another view, after moved spheres, after a
+    preparation without a render, and the brute-force variant between
+    ordered renders: every image equals the row-order render of its own
+    view (1080p workload)."""
+    wl = scenegen.make_workload(1)
+    W, H, D = wl.W, wl.H, wl.depth
+    with rt.SceneHandle(wl.scene) as h:
+        for yaw in (0.0, 0.5, 3.0, 20.0, 0.0):
+            cam = Camera(yaw_deg=yaw)
+            a, ia, _ = _render_flags(rt, h, wl, 0, camera=cam)
+            b, ib, _ = _render_flags(rt, h, wl, rt.RT_RENDER_ROW_ORDER, camera=cam)
+            assert torch.equal(a, b) and torch.equal(ia, ib), yaw
+        s2 = scenegen.random_scene(np.random.default_rng(5), wl.scene.n_spheres, 2,
+                                   box=scenegen.BOX_MEDIUM)
+        rt.rt_scene_update(h.handle, s2)
+        wl2 = scenegen.Workload(wl.name, s2, wl.camera, W, H, D)
+        a, ia, _ = _render_flags(rt, h, wl2, 0)
+        rt.rt_render_prepare(h.handle, wl.camera, W, H)
+        rt.rt_render_prepare(h.handle, wl.camera, W, H)
+        c, ic, _ = _render_flags(rt, h, wl2, rt.RT_RENDER_CONES_READY)
+        bf, ibf, _ = _render_flags(rt, h, wl2, rt.RT_RENDER_NO_PREFILTER)
+        d, id_, _ = _render_flags(rt, h, wl2, 0)
+        b, ib, _ = _render_flags(rt, h, wl2, rt.RT_RENDER_ROW_ORDER)
+        for x, ix in ((a, ia), (c, ic), (bf, ibf), (d, id_)):
+            assert torch.equal(x, b) and torch.equal(ix, ib)
+
+
+def test_tile_order_of_another_size_is_not_used(rt):
+    """A preparation made for one image size leaves rt_render_ex with
+    RT_RENDER_CONES_READY at another size in row order: the image equals
+    rt_render's at that size (a 720p order table, then a 1080p render, and
+    back)."""
+    wl = scenegen.make_workload(1)
+    D = wl.depth
+    with rt.SceneHandle(wl.scene) as h:
+        for (W0, H0), (W1, H1) in (((1280, 720), (1920, 1080)), ((1920, 1080), (1280, 720))):
+            want = torch.empty((H1, W1, 3), device="cuda")
+            rt.rt_render(h.handle, wl.camera, W1, H1, D, want)
+            rt.rt_render_prepare(h.handle, wl.camera, W0, H0)
+            got = torch.empty_like(want)
+            rt.rt_render_ex(h.handle, wl.camera, W1, H1, D, got, None, None,
+                            rt.RT_RENDER_CONES_READY)
+            torch.cuda.synchronize()
+            assert torch.equal(want, got), (W0, H0, W1, H1)
+
+
+def test_tile_order_with_camera_inside_a_sphere_and_many_planes(rt):
+    """Cost estimates of degenerate views: the eye inside a sphere (every
+    direction touches it), planes seen from behind and mirror images behind
+    their plane; 16 planes x 60 spheres = 1020 entries.  The ordered render
+    equals the row-order one."""
+    rng = np.random.default_rng(77)
+    planes = [(0.0, 1.0, 0.0, -1.0)]
+    for k in range(15):
+        m = rng.normal(size=3)
+        m /= np.linalg.norm(m)
+        planes.append((m[0], m[1], m[2], float(rng.uniform(-40.0, 40.0))))
+    s = scenegen.random_scene(rng, 60, 2, box=scenegen.BOX_MEDIUM,
+                              planes=np.array(planes, dtype=np.float32))
+    cam = Camera(eye=tuple(float(v) for v in s.sphere_geom[3, :3]))
+    wl = scenegen.Workload("inside", s, cam, 1280, 720, 2)
+    with rt.SceneHandle(s) as h:
+        a, ia, _ = _render_flags(rt, h, wl, 0)
+        b, ib, _ = _render_flags(rt, h, wl, rt.RT_RENDER_ROW_ORDER)
     assert torch.equal(a, b) and torch.equal(ia, ib)
