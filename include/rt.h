@@ -215,9 +215,9 @@ rt_status rt_render(rt_scene scene, const rt_camera* cam, int32_t W, int32_t H, 
                                       out-of-bounds access; the tile order of
                                       that preparation is used only if it was
                                       made for the same W x H */
-#define RT_RENDER_ROW_ORDER 4u     /* rt_render_ex only: take the tiles in
-                                      row order and record no durations; the
-                                      same image bits */
+#define RT_RENDER_ROW_ORDER 4u     /* rt_render_ex and rt_render_soft:
+                                      take the tiles in row order and record
+                                      no durations; the same image bits */
 
 /* rt_render with flags (0 = rt_render); the same two launches (one with
  * RT_RENDER_CONES_READY) and the same rule for calls on one scene. */
@@ -249,11 +249,16 @@ rt_status rt_render_prepare(rt_scene scene, const rt_camera* cam, int32_t W, int
  *   samples       1 .. RT_MAX_SAMPLES; samples == 1 or light_radius == 0 is
  *                 the point light, rendered exactly as rt_render_ex;
  *   light_radius  finite, >= 0, scene units;
- *   rgb_out, id_out, flags as rt_render_ex.  No records: the adjoint and the
- *   batched launch take point lights.
- * Launches two kernels (the sample table, then the render); no allocation,
- * capture-safe.  Renders of one scene must not overlap in time (the sample
- * table and the eye cones live in the scene's buffer). */
+ *   rgb_out, id_out as rt_render_ex; flags RT_RENDER_NO_PREFILTER and
+ *   RT_RENDER_ROW_ORDER.  No records: the adjoint and the batched launch take
+ *   point lights.
+ * Launches three kernels (the preparation as rt_render's, the sample table,
+ * the render): like rt_render it records every tile's duration and takes the
+ * tiles longest first by the record of the last soft-shadow render of the
+ * scene at this W x H (hard- and soft-shadow renders keep apart records; an
+ * image takes the same bits in any order).  No allocation, capture-safe.
+ * Renders of one scene must not overlap in time (the sample table, the eye
+ * cones and the tile schedule live in the scene's buffer). */
 rt_status rt_render_soft(rt_scene scene, const rt_camera* cam, int32_t W, int32_t H,
                          int32_t depth, int32_t samples, float light_radius, float* rgb_out,
                          int32_t* id_out, uint32_t flags, void* stream);

@@ -32,7 +32,7 @@ __device__ __forceinline__ int tile_of(const SceneDev& s) {
   const int n = (int)(gridDim.x * gridDim.y);
   const int b = blockIdx.y * gridDim.x + blockIdx.x;
   if (!(s.sched_mode & kSchedOrdered)) return b;
-  return min(max(((const RT_CONSTANT int*)(s.sched + kSchedOrder))[b], 0), n - 1);
+  return min(max(((const RT_CONSTANT int*)(s.sched + kSchedOrder))[sched_slot(b, n)], 0), n - 1);
 }
 
 // The tile's duration for the next render's order: core clocks since t_start,
@@ -108,8 +108,14 @@ __global__ __launch_bounds__(kRenderThreads) void render_soft_kernel(SceneDev s,
                                                            float* __restrict__ rgb,
                                                            int32_t* __restrict__ id_out) {
   const int lane = threadIdx.x;
-  const int x = blockIdx.x * kTile + (lane & 7);
-  const int y = blockIdx.y * kTile + (lane >> 3);
+  // the tile: row order, or the scene's order (as render_kernel)
+  const int t = tile_of(s);
+  const int ty = t / (int)gridDim.x;
+  const int tx = t - ty * (int)gridDim.x;
+  __shared__ uint64_t s_start;
+  if (s.sched_mode & kSchedRecord) s_start = __builtin_amdgcn_s_memtime();
+  const int x = tx * kTile + (lane & 7);
+  const int y = ty * kTile + (lane >> 3);
   const bool live = x < c.W && y < c.H;
   if (!wave_any(live)) return;
   const int64_t pix = live ? (int64_t)y * c.W + x : 0;
@@ -125,6 +131,7 @@ __global__ __launch_bounds__(kRenderThreads) void render_soft_kernel(SceneDev s,
     rgb[3 * pix + 2] = cb;
     if (id_out) id_out[pix] = prim;
   }
+  if (s.sched_mode & kSchedRecord) record_duration(s, tile_of(s), s_start);
 }
 
 // Sample points of the sunflower arrangement: point i of n at radius
@@ -143,7 +150,7 @@ __global__ void sample_table_kernel(int n, float radius, float2* __restrict__ ta
 
 hipError_t launch_render_soft(const rt_scene_s& sc, const CameraDev& c, int depth, int samples,
                               float radius, float* rgb, int32_t* ids, bool prefilter,
-                              hipStream_t stream) {
+                              int sched_mode, hipStream_t stream) {
   hipLaunchKernelGGL(sample_table_kernel, dim3((samples + 255) / 256), dim3(256), 0, stream,
                      samples, radius, sc.soft_table);
   hipError_t e = hipGetLastError();
@@ -158,8 +165,9 @@ hipError_t launch_render_soft(const rt_scene_s& sc, const CameraDev& c, int dept
                                : render_soft_kernel<false, SkyBackground>)
                   : (prefilter ? render_soft_kernel<true, PlainBackground>
                                : render_soft_kernel<false, PlainBackground>);
-  hipLaunchKernelGGL(kern, grid, dim3(kRenderThreads), 0, stream, sc.view(), c, depth, sh, rgb,
-                     ids);
+  SceneDev s = sc.view();
+  s.sched_mode = sched_mode;
+  hipLaunchKernelGGL(kern, grid, dim3(kRenderThreads), 0, stream, s, c, depth, sh, rgb, ids);
   return hipGetLastError();
 }
 

@@ -382,19 +382,43 @@ rt_status rt_render(rt_scene sc, const rt_camera* cam, int32_t W, int32_t H, int
   return rt_render_ex(sc, cam, W, H, depth, rgb_out, id_out, rec, 0, stream);
 }
 
-// The launch before a hard-shadow render: eye cones and, where scheduling
-// applies, the tile order from the durations the last render of this size
-// recorded (remembered for RT_RENDER_CONES_READY renders of the same size).
-static hipError_t prepare_render(rt_scene_s* sc, const CameraDev& c, bool row_order,
+// The launch before a render of `kind` (hard or soft shadows): eye cones and,
+// where scheduling applies, the tile order from the durations the last render
+// of this kind and size recorded (remembered for RT_RENDER_CONES_READY
+// renders of the same size), and the record the render may write.
+static hipError_t prepare_render(rt_scene_s* sc, const CameraDev& c, bool row_order, int kind,
                                  hipStream_t stream) {
   const bool sched = !row_order && schedule_applies(*sc, c.W, c.H);
   bool ordered = false;
-  hipError_t e = launch_prepare(*sc, c, sched, &ordered, stream);
-  sc->order_W = (e == hipSuccess && ordered) ? c.W : 0;
-  sc->order_H = (e == hipSuccess && ordered) ? c.H : 0;
-  sc->rec_W = (e == hipSuccess && sched) ? c.W : 0;
-  sc->rec_H = (e == hipSuccess && sched) ? c.H : 0;
+  hipError_t e = launch_prepare(*sc, c, sched, kind, &ordered, stream);
+  const bool ok = e == hipSuccess;
+  sc->order_W = (ok && ordered) ? c.W : 0;
+  sc->order_H = (ok && ordered) ? c.H : 0;
+  sc->rec_W = (ok && sched) ? c.W : 0;
+  sc->rec_H = (ok && sched) ? c.H : 0;
+  sc->sched_kind = kind;
   return e;
+}
+
+// Schedule mode of a render of `kind` at W x H after its preparation: the
+// prepared order if it was made for this kind and size, and a record of its
+// tile durations into the histogram set the preparation zeroed (once).
+static int schedule_mode(const rt_scene_s* sc, int W, int H, int kind, bool row_order,
+                         bool brute) {
+  if (row_order || brute || !schedule_applies(*sc, W, H) || sc->sched_kind != kind) return 0;
+  int mode = 0;
+  if (sc->order_W == W && sc->order_H == H) mode |= kSchedOrdered;
+  if (sc->rec_W == W && sc->rec_H == H) mode |= kSchedRecord | (sc->hist_set ? 0 : kSchedHistSet1);
+  return mode;
+}
+
+static void schedule_recorded(rt_scene_s* sc, int mode, int W, int H, int kind) {
+  if (!(mode & kSchedRecord)) return;
+  sc->hist_set ^= 1;   // the set just filled holds this render's record
+  sc->hist_W = W;
+  sc->hist_H = H;
+  sc->hist_kind = kind;
+  sc->rec_W = sc->rec_H = 0;
 }
 
 rt_status rt_render_prepare(rt_scene sc, const rt_camera* cam, int32_t W, int32_t H,
@@ -402,7 +426,8 @@ rt_status rt_render_prepare(rt_scene sc, const rt_camera* cam, int32_t W, int32_
   if (!sc) return fail(RT_ERR_INVALID_ARG, "scene is NULL");
   rt_status st = validate_camera(cam, W, H, 0);
   if (st != RT_OK) return st;
-  return hip_fail(prepare_render(sc, camera_dev(*cam, W, H), false, (hipStream_t)stream),
+  return hip_fail(prepare_render(sc, camera_dev(*cam, W, H), false, kSchedHard,
+                                 (hipStream_t)stream),
                   "prepare launch");
 }
 
@@ -420,28 +445,15 @@ rt_status rt_render_ex(rt_scene sc, const rt_camera* cam, int32_t W, int32_t H, 
   const bool row_order = flags & RT_RENDER_ROW_ORDER;
   hipError_t e = (flags & RT_RENDER_CONES_READY)
                      ? hipSuccess
-                     : prepare_render(sc, c, row_order, (hipStream_t)stream);
+                     : prepare_render(sc, c, row_order, kSchedHard, (hipStream_t)stream);
   SceneDev s = sc->view();
   // the brute-force variant keeps row order and records nothing
-  const bool sched =
-      !row_order && !(flags & RT_RENDER_NO_PREFILTER) && schedule_applies(*sc, W, H);
-  // the order of the last prepare, if it was made for this image size
-  if (sched && sc->order_W == W && sc->order_H == H) s.sched_mode |= kSchedOrdered;
-  // every tile records its duration for the next render of this size, into
-  // the histogram set the last prepare zeroed (if it prepared this size and
-  // no render has recorded since)
-  const bool record = sched && sc->rec_W == W && sc->rec_H == H;
-  if (record) s.sched_mode |= kSchedRecord | (sc->hist_set ? 0 : kSchedHistSet1);
+  s.sched_mode = schedule_mode(sc, W, H, kSchedHard, row_order, flags & RT_RENDER_NO_PREFILTER);
   if (e == hipSuccess)
     e = launch_render(s, c, depth, rgb_out, id_out, rec ? rec->ids : nullptr,
                       rec ? rec->lit : nullptr, !(flags & RT_RENDER_NO_PREFILTER),
                       (hipStream_t)stream);
-  if (e == hipSuccess && record) {
-    sc->hist_set ^= 1;   // the set just filled holds this render's record
-    sc->hist_W = W;
-    sc->hist_H = H;
-    sc->rec_W = sc->rec_H = 0;
-  }
+  if (e == hipSuccess) schedule_recorded(sc, s.sched_mode, W, H, kSchedHard);
   return hip_fail(e, "render launch");
 }
 
@@ -455,16 +467,20 @@ rt_status rt_render_soft(rt_scene sc, const rt_camera* cam, int32_t W, int32_t H
     return fail(RT_ERR_INVALID_ARG, "light_radius must be finite and >= 0");
   if (samples == 1 || light_radius == 0.0f)   // the point light
     return rt_render_ex(sc, cam, W, H, depth, rgb_out, id_out, nullptr, flags, stream);
-  if (flags & ~(uint32_t)RT_RENDER_NO_PREFILTER)
+  if (flags & ~(uint32_t)(RT_RENDER_NO_PREFILTER | RT_RENDER_ROW_ORDER))
     return fail(RT_ERR_INVALID_ARG, "unknown render flags 0x%x", flags);
   rt_status st = validate_camera(cam, W, H, depth);
   if (st != RT_OK) return st;
   if (!rgb_out) return fail(RT_ERR_INVALID_ARG, "rgb_out is NULL");
   CameraDev c = camera_dev(*cam, W, H);
-  hipError_t e = launch_eye_cones(*sc, c, (hipStream_t)stream);
+  const bool row_order = flags & RT_RENDER_ROW_ORDER;
+  hipError_t e = prepare_render(sc, c, row_order, kSchedSoft, (hipStream_t)stream);
+  const int mode =
+      schedule_mode(sc, W, H, kSchedSoft, row_order, flags & RT_RENDER_NO_PREFILTER);
   if (e == hipSuccess)
     e = launch_render_soft(*sc, c, depth, samples, light_radius, rgb_out, id_out,
-                           !(flags & RT_RENDER_NO_PREFILTER), (hipStream_t)stream);
+                           !(flags & RT_RENDER_NO_PREFILTER), mode, (hipStream_t)stream);
+  if (e == hipSuccess) schedule_recorded(sc, mode, W, H, kSchedSoft);
   return hip_fail(e, "soft render launch");
 }
 

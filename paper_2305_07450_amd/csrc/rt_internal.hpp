@@ -39,8 +39,10 @@ struct rt_scene_s {
   uint8_t* sched = nullptr;
   int hist_set = 0;                // histogram set holding the last record
   int hist_W = 0, hist_H = 0;      // image of the recorded duration bins (0: none)
+  int hist_kind = 0;               // kernel that recorded them (kSchedHard, kSchedSoft)
   int order_W = 0, order_H = 0;    // image the last prepare ordered (0: none)
   int rec_W = 0, rec_H = 0;        // image the next render may record (other set zeroed)
+  int sched_kind = 0;              // kernel the last prepare prepared for
 
   rtk::SceneDev view() const {
     rtk::SceneDev s;
@@ -71,6 +73,9 @@ inline dim3 render_grid(int W, int H) {
 // least kSchedMinTiles tiles (fewer all start at once) and at most
 // kSchedMaxTiles (the scene's tables).
 constexpr int kSchedMinTiles = 4096;
+// Kernels whose tile durations are recorded apart (a record is used only by
+// the same kernel): hard-shadow and soft-shadow renders.
+constexpr int kSchedHard = 0, kSchedSoft = 1;
 
 // Workgroups of the persistent adjoint grid (one partial-gradient slot each).
 constexpr int kAdjointBlocks = 1024;
@@ -104,12 +109,13 @@ hipError_t launch_eye_cones(const rt_scene_s& sc, const CameraDev& c, hipStream_
 // scene's tile order for a render of c.W x c.H from the durations the last
 // render of that size recorded (*ordered: an order was written), and the
 // zeroed histogram the following render records into.
-hipError_t launch_prepare(rt_scene_s& sc, const CameraDev& c, bool schedule, bool* ordered,
-                          hipStream_t stream);
+hipError_t launch_prepare(rt_scene_s& sc, const CameraDev& c, bool schedule, int kind,
+                          bool* ordered, hipStream_t stream);
 bool schedule_applies(const rt_scene_s& sc, int W, int H);
+// sched_mode: the tile schedule's mode bits (0: row order, no record).
 hipError_t launch_render_soft(const rt_scene_s& sc, const CameraDev& c, int depth, int samples,
                               float radius, float* rgb, int32_t* ids, bool prefilter,
-                              hipStream_t stream);
+                              int sched_mode, hipStream_t stream);
 
 // The render kernels' entry addresses, for graph nodes built by hand: the
 // hard-shadow render without records, and the soft-shadow render, with or

@@ -42,7 +42,7 @@ struct PrepareArgs {
   int hist_chunks;          // histogram chunks of kSchedHistChunk tiles
   const uint32_t* hist;     // [hist_chunks][kSchedBins] its chunk histograms
   uint32_t* next_hist;      // [kSchedChunks][kSchedBins] zeroed for the coming render, or NULL
-  int32_t* order;           // [n_tiles] out: tiles, longest first
+  int32_t* order;           // out: tiles, longest first, position p at sched_slot(p)
 };
 
 __global__ __launch_bounds__(kPrepThreads) void prepare_kernel(PrepareArgs a) {
@@ -107,13 +107,13 @@ __global__ __launch_bounds__(kPrepThreads) void prepare_kernel(PrepareArgs a) {
   __syncthreads();
   if (!valid) return;
   if (s_bad) {
-    a.order[t] = t;
+    a.order[sched_slot(t, a.n_tiles)] = t;
     return;
   }
   uint32_t pos = s_before[k] + rank;
   for (int kk = kSchedBins - 1; kk > k; --kk) pos += s_total[kk];   // longer bins first
   for (int w = 0; w < wave; ++w) pos += s_wave[w][k];
-  if (pos < (uint32_t)a.n_tiles) a.order[pos] = t;
+  if (pos < (uint32_t)a.n_tiles) a.order[sched_slot((int)pos, a.n_tiles)] = t;
 }
 
 bool schedule_applies(const rt_scene_s& sc, int W, int H) {
@@ -122,8 +122,8 @@ bool schedule_applies(const rt_scene_s& sc, int W, int H) {
   return sc.sched && tiles >= kSchedMinTiles && tiles <= kSchedMaxTiles;
 }
 
-hipError_t launch_prepare(rt_scene_s& sc, const CameraDev& c, bool schedule, bool* ordered,
-                          hipStream_t stream) {
+hipError_t launch_prepare(rt_scene_s& sc, const CameraDev& c, bool schedule, int kind,
+                          bool* ordered, hipStream_t stream) {
   PrepareArgs a;
   a.geom = sc.geom;
   a.rad = sc.rad;
@@ -136,7 +136,8 @@ hipError_t launch_prepare(rt_scene_s& sc, const CameraDev& c, bool schedule, boo
   const dim3 g = render_grid(c.W, c.H);
   a.n_tiles = (int)(g.x * g.y);
   // an order from the last render's measured bins, if it rendered this size
-  const bool from_history = schedule && sc.hist_W == c.W && sc.hist_H == c.H;
+  const bool from_history =
+      schedule && sc.hist_W == c.W && sc.hist_H == c.H && sc.hist_kind == kind;
   a.chunks = from_history ? (a.n_tiles + kSchedChunk - 1) / kSchedChunk : 0;
   a.hist_chunks = (a.n_tiles + kSchedHistChunk - 1) / kSchedHistChunk;
   uint32_t* hist = (uint32_t*)(sc.sched + kSchedHist);

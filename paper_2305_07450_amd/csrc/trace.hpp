@@ -64,6 +64,14 @@ constexpr size_t kSchedBin = kSchedOrder + 4 * (size_t)kSchedMaxTiles;     // ui
 constexpr size_t kSchedHist = kSchedBin + (size_t)kSchedMaxTiles;
 constexpr size_t kSchedBytes = kSchedHist + 2 * 4 * (size_t)kSchedChunks * kSchedBins;
 constexpr int kSchedOrdered = 1, kSchedRecord = 2, kSchedHistSet1 = 4;
+// Slot of launch position b (of n) in the order table.  Workgroups are dealt
+// to the 8 XCDs in turn (b mod 8), each XCD with an L2 of its own, so the
+// table keeps every XCD's positions together: an XCD reads its eighth of the
+// table, not a share of every cache line of it.  A permutation of [0, n) into
+// [0, 8 ceil(n / 8)), within kSchedMaxTiles for n up to it.
+__host__ __device__ __forceinline__ int sched_slot(int b, int n) {
+  return (b & 7) * ((n + 7) >> 3) + (b >> 3);
+}
 
 // Sphere tables (geom, eye_cone, light_cone) hold n4 = round_up(N, kGroup)
 // entries plus one more group, so the loops below read kGroup spheres with

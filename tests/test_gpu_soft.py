@@ -122,4 +122,33 @@ def test_soft_rejects_bad_arguments(rt):
             with pytest.raises(rt.RtError):
                 rt.rt_render_soft(h.handle, Camera(), 10, 10, 1, n, R, out)
         with pytest.raises(rt.RtError):
-            rt.rt_render_soft(h.handle, Camera(), 10, 10, 1, 8, 0.5, out, None, 4)
+            rt.rt_render_soft(h.handle, Camera(), 10, 10, 1, 8, 0.5, out, None, 8)
+
+
+def test_soft_tile_order_changes_no_bits(rt):
+    """rt_render_soft records its tiles' durations and the next soft render of
+    the scene at that size takes the tiles longest first; hard-shadow renders
+    in between record for themselves.  Every image equals the row-order soft
+    render bit for bit (bench scene, 1280x720, 14 400 tiles)."""
+    s = scenegen.make_workload(1).scene
+    cam = Camera(yaw_deg=1.0)
+    W, H, D, n, R = 1280, 720, 3, 48, 0.5
+    log("case soft tile order", W, H, D, n, R)
+
+    def soft(h, flags):
+        img = torch.full((H, W, 3), float("nan"), device="cuda")
+        ids = torch.full((H, W), -7, dtype=torch.int32, device="cuda")
+        rt.rt_render_soft(h.handle, cam, W, H, D, n, R, img, ids, flags)
+        torch.cuda.synchronize()
+        return img, ids
+
+    with rt.SceneHandle(s) as h:
+        want, iw = soft(h, rt.RT_RENDER_ROW_ORDER)
+        hard = torch.empty((H, W, 3), device="cuda")
+        for k in range(5):   # records, ordered, ordered; a hard render; again
+            if k == 3:
+                rt.rt_render(h.handle, cam, W, H, D, hard)
+            a, ia = soft(h, 0)
+            assert torch.equal(a, want) and torch.equal(ia, iw), k
+        bf, ibf = soft(h, rt.RT_RENDER_NO_PREFILTER)
+        assert torch.equal(bf, want) and torch.equal(ibf, iw)
