@@ -52,6 +52,19 @@ def frac_of_peak(flops: float, ms: float) -> float:
     return flops / (ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS
 
 
+def executed_fp32(prof: dict, ms: float):
+    """All FP32 arithmetic the render kernel issues (rocprofv3 VALU counts x
+    lane utilisation, from the committed profile of this kernel source), per
+    launch and as a rate over `ms`; None when the source has changed."""
+    f = prof.get("executed_fp32_flops_per_launch")
+    if not f:
+        return None
+    return {"flops_per_launch": f, "tflops": round(f / (ms * 1e-3) / 1e12, 3),
+            "frac": round(frac_of_peak(f, ms), 4),
+            "source": "(2 x FMA_F32 + ADD_F32 + MUL_F32) x 64 x lane utilisation, "
+                      "profiles/render_traffic.json"}
+
+
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "render_traffic.json")
 ADJOINT_FILE = os.path.join(ROOT, "profiles", "adjoint_fp32.json")
 CSRC = "paper_2305_07450_amd/csrc/"
@@ -297,6 +310,30 @@ def bench_fwd_bwd(rt, scenegen, stream, steps):
             "work_per_frame": counts}
 
 
+def adjoint_launches(rt, scenegen, n):
+    """The forward+backward workload for a profiler: one render with records,
+    then n rt_render_backward launches from them and n re-traced."""
+    import torch
+    prob = scenegen.make_diff_problem()
+    wl = prob.workload
+    W, H, D = wl.W, wl.H, wl.depth
+    N, L = wl.scene.n_spheres, wl.scene.n_lights
+    with rt.SceneHandle(wl.scene) as h:
+        rgb = torch.empty((H, W, 3), device="cuda")
+        grad = torch.ones((H, W, 3), device="cuda")
+        g = {k: torch.empty(sh, device="cuda") for k, sh in (
+            ("albedo", (N, 3)), ("refl", (N,)), ("center", (N, 3)), ("light_pos", (L, 3)),
+            ("light_int", (L,)))}
+        rec = rt.Records(W, H, D)
+        rt.rt_render(h.handle, wl.camera, W, H, D, rgb, None, rec)
+        for _ in range(n):
+            rt.rt_render_backward(h.handle, wl.camera, W, H, D, grad, g, rec)
+        for _ in range(n):
+            rt.rt_render_backward(h.handle, wl.camera, W, H, D, grad, g, None)
+        torch.cuda.synchronize()
+    print(json.dumps({"workload": wl.name, "adjoint_launches": n}), flush=True)
+
+
 def bench_batch(rt, scenegen, stream, steps):
     """64 scenes of uneven size in one graph-captured persistent launch, against
     64 rt_render calls back to back on one stream."""
@@ -469,8 +506,15 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a kernel of "
                          "known traffic, to calibrate HBM byte counters)")
+    ap.add_argument("--adjoint-launches", type=int, default=0,
+                    help="only run the forward+backward workload: one render with records, "
+                         "then this many backward launches from the records and as many "
+                         "re-traced (a short run to profile the adjoint kernel), and exit")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the batched and forward+backward measurements")
+                    help="time only the headline render (no row-order, moving-camera, "
+                         "first-render, brute-force, batched or forward+backward "
+                         "measurements), so that a profile of the run sees the ordered "
+                         "render kernel almost only")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -488,6 +532,9 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    if args.adjoint_launches:
+        adjoint_launches(rt, scenegen, args.adjoint_launches)
+        return
     wl = scenegen.make_workload(args.workload)
     W, H, D = wl.W, wl.H, wl.depth
     dev = torch.device("cuda:0")
@@ -517,24 +564,27 @@ def main():
     # the first render of a freshly uploaded scene (row order, recording), and
     # a camera that turns 0.05 degrees a frame (each order measured on the
     # previous, different view)
-    row = lambda: rt.rt_render_ex(h.handle, wl.camera, W, H, D, rgb, None, None,
-                                  rt.RT_RENDER_ROW_ORDER, stream)
-    row_gpu, row_wall = time_steps(row, args.steps, 10, stream)
-    yaws = [0.05 * i for i in range(50)] + [0.05 * (50 - i) for i in range(50)]
-    cams = [scenegen.Camera(yaw_deg=y) for y in yaws]
-    turn = [0]
-
-    def moving():
-        turn[0] += 1
-        rt.rt_render(h.handle, cams[turn[0] % len(cams)], W, H, D, rgb, None, None, stream)
-    mov_gpu, mov_wall = time_steps(moving, args.steps, 10, stream)
     schedule = {
         "order": "tiles longest first, by the durations the previous render of the scene at "
-                 "this size measured; the first render of a size takes row order",
-        "row_order_ms_per_step": round(max(row_gpu, row_wall), 5),
-        "first_render_ms": first_render_ms(rt, wl, rgb, stream),
-        "moving_camera_ms_per_step": round(max(mov_gpu, mov_wall), 5),
-        "moving_camera": "yaw 0 to 2.45 degrees and back in steps of 0.05 degrees, one a frame"}
+                 "this size measured; the first render of a size takes row order"}
+    if not args.no_extras:
+        row = lambda: rt.rt_render_ex(h.handle, wl.camera, W, H, D, rgb, None, None,
+                                      rt.RT_RENDER_ROW_ORDER, stream)
+        row_gpu, row_wall = time_steps(row, args.steps, 10, stream)
+        yaws = [0.05 * i for i in range(50)] + [0.05 * (50 - i) for i in range(50)]
+        cams = [scenegen.Camera(yaw_deg=y) for y in yaws]
+        turn = [0]
+
+        def moving():
+            turn[0] += 1
+            rt.rt_render(h.handle, cams[turn[0] % len(cams)], W, H, D, rgb, None, None, stream)
+        mov_gpu, mov_wall = time_steps(moving, args.steps, 10, stream)
+        schedule.update({
+            "row_order_ms_per_step": round(max(row_gpu, row_wall), 5),
+            "first_render_ms": first_render_ms(rt, wl, rgb, stream),
+            "moving_camera_ms_per_step": round(max(mov_gpu, mov_wall), 5),
+            "moving_camera": "yaw 0 to 2.45 degrees and back in steps of 0.05 degrees, one "
+                             "a frame"})
     ids = torch.empty((H, W), dtype=torch.int32, device=dev)
     rt.rt_render(h.handle, wl.camera, W, H, D, rgb, ids, None, stream)
     torch.cuda.synchronize()
@@ -571,6 +621,7 @@ def main():
                      "kernel": "render_kernel (culled: cone tests and wave bounds)",
                      "kernel_ms": round(ms_kernel, 5),
                      "flops_per_launch": flops,
+                     "executed_fp32": executed_fp32(prof, ms_kernel),
                      "counted": "exact ray-sphere tests x 16 FLOP + ray-plane tests x 12 FLOP "
                                 "that the kernel executes, once per ray whose result can still "
                                 "matter (rt_render_counts [5], [6])"},
