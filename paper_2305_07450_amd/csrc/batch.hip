@@ -45,15 +45,20 @@ using Shape = TunedShape;
 
 __global__ void reset_counter_kernel(unsigned int* counter) { *counter = 0u; }
 
-// Eye cones of every job's spheres (grid.y = job), into the batch's own table.
+// Eye cones and eye - centre table of every job's spheres (grid.y = job), into
+// the batch's own tables (the job's eye_cone and eye_oc point there), with the
+// arithmetic of the single-image eye-cone kernel.
 __global__ void batch_cone_kernel(const BatchJob* __restrict__ jobs, float4* const* cones) {
   const BatchJob& j = jobs[blockIdx.y];
+  float4* oc = const_cast<float4*>(j.s.eye_oc);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < j.s.n_spheres) {
     float4 g = j.s.geom[i];
     cones[blockIdx.y][i] = sphere_cone(j.c.ex, j.c.ey, j.c.ez, g.x, g.y, g.z, j.s.rad[i].x);
+    oc[i] = make_float4(j.c.ex - g.x, j.c.ey - g.y, j.c.ez - g.z, g.w);
   } else if (i < j.s.n4 + kGroup) {
     cones[blockIdx.y][i] = make_float4(0.0f, 0.0f, 0.0f, kPadConeW);
+    oc[i] = make_float4(0.0f, 0.0f, 0.0f, kPadR2);
   }
 }
 
@@ -136,7 +141,8 @@ struct rt_batch_s {
   Shape shape{};
   BatchJob* jobs = nullptr;     // device
   TileRef* queue = nullptr;     // device
-  float4* cones = nullptr;      // device: eye cones of every job's spheres
+  float4* cones = nullptr;      // device: eye cones of every job's spheres, then their
+                                // eye - centre tables (the same offsets past the cones)
   float4** cone_ptr = nullptr;  // device: start of each job's cones
   int max_spheres = 0;
   unsigned int* counter = nullptr;
@@ -347,7 +353,8 @@ rt_status batch_create(int32_t n, const rt_scene* scenes, const rt_camera* cams,
   }
   int dev = 0, cus = 256;
   hipError_t e = hipGetDevice(&dev);
-  if (e == hipSuccess) e = hipMalloc(&b->cones, sizeof(float4) * std::max<size_t>(total_spheres, 1));
+  if (e == hipSuccess)
+    e = hipMalloc(&b->cones, 2 * sizeof(float4) * std::max<size_t>(total_spheres, 1));
   if (e == hipSuccess) e = hipMalloc(&b->cone_ptr, sizeof(float4*) * n);
   if (e == hipSuccess) {
     std::vector<float4*> ptrs(n);
@@ -355,6 +362,7 @@ rt_status batch_create(int32_t n, const rt_scene* scenes, const rt_camera* cams,
     for (int i = 0; i < n; ++i) {
       ptrs[i] = b->cones + off;
       b->host_jobs[i].s.eye_cone = ptrs[i];
+      b->host_jobs[i].s.eye_oc = ptrs[i] + total_spheres;
       off += pad_spheres(scenes[i]->n_spheres) + kGroup;
     }
     e = hipMemcpy(b->cone_ptr, ptrs.data(), sizeof(float4*) * n, hipMemcpyHostToDevice);

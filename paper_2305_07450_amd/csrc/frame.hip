@@ -35,12 +35,14 @@ struct PrepArgs {
   const float4* light;
   float4* light_cone;
   float4* eye_cone;
+  float4* light_oc;
+  float4* eye_oc;
 };
 
 // One lane per sphere slot (padding included): the new centre, the cones
-// of the sphere seen from every light, then from the eye.  The cones are the
-// same function of the same floats as at upload and in the eye-cone kernel,
-// so a frame renders the bits that rt_scene_update + rt_render give.
+// and o - c of the sphere seen from every light, then from the eye.  They are
+// the same functions of the same floats as at upload and in the eye-cone
+// kernel, so a frame renders the bits that rt_scene_update + rt_render give.
 __global__ void frame_prep_kernel(PrepArgs a) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < a.N) {
@@ -54,11 +56,14 @@ __global__ void frame_prep_kernel(PrepArgs a) {
       for (int l = 0; l < a.L; ++l) {
         const float4 q = a.light[l];
         a.light_cone[(int64_t)l * a.n4 + i] = sphere_cone(q.x, q.y, q.z, g.x, g.y, g.z, r);
+        a.light_oc[(int64_t)l * a.n4 + i] = make_float4(q.x - g.x, q.y - g.y, q.z - g.z, g.w);
       }
     }
     a.eye_cone[i] = sphere_cone(a.ex, a.ey, a.ez, g.x, g.y, g.z, a.rad[i].x);
+    a.eye_oc[i] = make_float4(a.ex - g.x, a.ey - g.y, a.ez - g.z, g.w);
   } else if (i < a.n4 + kGroup) {
     a.eye_cone[i] = make_float4(0.0f, 0.0f, 0.0f, kPadConeW);
+    a.eye_oc[i] = make_float4(0.0f, 0.0f, 0.0f, kPadR2);
   }
 }
 
@@ -162,6 +167,8 @@ void fill_args(const rt_frame_s* f, const rt_camera& cam, int depth, int samples
   a.prep.light = sc.light;
   a.prep.light_cone = sc.light_cone;
   a.prep.eye_cone = sc.eye_cone;
+  a.prep.light_oc = sc.light_oc;
+  a.prep.eye_oc = sc.eye_oc;
   a.prep_args[0] = &a.prep;
   a.prep_p.func = (void*)frame_prep_kernel;
   a.prep_p.gridDim = dim3((n4 + kGroup + 255) / 256);

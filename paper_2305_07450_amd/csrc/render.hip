@@ -249,14 +249,17 @@ hipError_t launch_render(const SceneDev& s, const CameraDev& c, int depth, float
 // (r, 1/r), sphere and plane materials in one id-indexed table.
 __global__ void pack_kernel(RawScene raw, int N, int P, int L, float4* geom, float2* rad,
                             float4* mat, float* shine, float4* pgeom, float4* light,
-                            float4* light_cone) {
+                            float4* light_cone, float4* light_oc) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int n4 = pad_spheres(N);
   if (i >= N && i < n4 + kGroup) {
     // padding spheres: never hit, never inside a cone
     geom[i] = make_float4(0.0f, 0.0f, 0.0f, kPadR2);
     for (int l = 0; l < L; ++l)
-      if (i < n4 || l == L - 1) light_cone[(int64_t)l * n4 + i] = make_float4(0.f, 0.f, 0.f, kPadConeW);
+      if (i < n4 || l == L - 1) {
+        light_cone[(int64_t)l * n4 + i] = make_float4(0.f, 0.f, 0.f, kPadConeW);
+        light_oc[(int64_t)l * n4 + i] = make_float4(0.f, 0.f, 0.f, kPadR2);
+      }
   }
   if (i < N) {
     const float* g = raw.sphere_geom + 4 * i;
@@ -269,6 +272,7 @@ __global__ void pack_kernel(RawScene raw, int N, int P, int L, float4* geom, flo
     for (int l = 0; l < L; ++l) {
       const float* q = raw.light + 4 * l;
       light_cone[(int64_t)l * n4 + i] = sphere_cone(q[0], q[1], q[2], g[0], g[1], g[2], r);
+      light_oc[(int64_t)l * n4 + i] = make_float4(q[0] - g[0], q[1] - g[1], q[2] - g[2], r * r);
     }
   }
   if (i < P) {
@@ -290,7 +294,7 @@ hipError_t launch_pack(const rt_scene_s& sc, const RawScene& raw, hipStream_t st
   if (sc.n_lights > n) n = sc.n_lights;
   hipLaunchKernelGGL(pack_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, raw,
                      sc.n_spheres, sc.n_planes, sc.n_lights, sc.geom, sc.rad, sc.mat, sc.shine,
-                     sc.pgeom, sc.light, sc.light_cone);
+                     sc.pgeom, sc.light, sc.light_cone, sc.light_oc);
   return hipGetLastError();
 }
 
@@ -307,13 +311,16 @@ hipError_t launch_sky_pack(const float* rgb, float4* sky, int texels, hipStream_
 }
 
 __global__ void eye_cone_kernel(const float4* __restrict__ geom, const float2* __restrict__ rad,
-                                int N, float ex, float ey, float ez, float4* __restrict__ out) {
+                                int N, float ex, float ey, float ez, float4* __restrict__ out,
+                                float4* __restrict__ oc) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < N) {
     float4 g = geom[i];
     out[i] = sphere_cone(ex, ey, ez, g.x, g.y, g.z, rad[i].x);
+    oc[i] = make_float4(ex - g.x, ey - g.y, ez - g.z, g.w);
   } else if (i < pad_spheres(N) + kGroup) {
     out[i] = make_float4(0.0f, 0.0f, 0.0f, kPadConeW);
+    oc[i] = make_float4(0.0f, 0.0f, 0.0f, kPadR2);
   }
 }
 
@@ -321,7 +328,7 @@ hipError_t launch_eye_cones(const rt_scene_s& sc, const CameraDev& c, hipStream_
   hipLaunchKernelGGL(eye_cone_kernel, dim3((pad_spheres(sc.n_spheres) + kGroup + 255) / 256), dim3(256), 0,
                      stream,
                      (const float4*)sc.geom, (const float2*)sc.rad, sc.n_spheres, c.ex, c.ey,
-                     c.ez, sc.eye_cone);
+                     c.ez, sc.eye_cone, sc.eye_oc);
   return hipGetLastError();
 }
 

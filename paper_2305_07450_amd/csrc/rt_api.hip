@@ -241,6 +241,8 @@ rt_status rt_scene_upload(const rt_scene_desc* d, void* stream, rt_scene* out) {
   size_t o_light = take(L * sizeof(float4));
   size_t o_eye_cone = take((N4 + kGroup) * sizeof(float4));
   size_t o_light_cone = take((L * N4 + kGroup) * sizeof(float4));
+  size_t o_eye_oc = take((N4 + kGroup) * sizeof(float4));
+  size_t o_light_oc = take((L * N4 + kGroup) * sizeof(float4));
   sc->staging_floats = 9 * N + 9 * P + 4 * L;
   size_t o_stage = take(sc->staging_floats * sizeof(float));
   size_t o_part = take((size_t)blocks * sc->grad_stride * sizeof(float));
@@ -263,6 +265,8 @@ rt_status rt_scene_upload(const rt_scene_desc* d, void* stream, rt_scene* out) {
   sc->light = (float4*)(base + o_light);
   sc->eye_cone = (float4*)(base + o_eye_cone);
   sc->light_cone = (float4*)(base + o_light_cone);
+  sc->eye_oc = (float4*)(base + o_eye_oc);
+  sc->light_oc = (float4*)(base + o_light_oc);
   sc->staging = (float*)(base + o_stage);
   sc->partials = (float*)(base + o_part);
   sc->soft_table = (float2*)(base + o_soft);

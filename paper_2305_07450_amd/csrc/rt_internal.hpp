@@ -27,6 +27,8 @@ struct rt_scene_s {
   float4* light = nullptr; // [L]
   float4* eye_cone = nullptr;    // [n4+kGroup] rebuilt for the camera of each call
   float4* light_cone = nullptr;  // [L*n4 + kGroup]  rows of n4, rebuilt by every upload/update
+  float4* eye_oc = nullptr;      // [n4+kGroup] eye - centre, r^2, with the eye cones
+  float4* light_oc = nullptr;    // [L*n4 + kGroup] light - centre, r^2, with the light cones
   float* staging = nullptr;     // raw copy of host desc arrays
   size_t staging_floats = 0;
   float2* soft_table = nullptr; // [RT_MAX_SAMPLES] shadow sample points of the last soft render
@@ -48,6 +50,7 @@ struct rt_scene_s {
     rtk::SceneDev s;
     s.geom = geom; s.rad = rad; s.mat = mat; s.shine = shine; s.pgeom = pgeom; s.light = light;
     s.eye_cone = eye_cone; s.light_cone = light_cone;
+    s.eye_oc = eye_oc; s.light_oc = light_oc;
     s.n4 = rtk::pad_spheres(n_spheres);
     s.n_spheres = n_spheres; s.n_planes = n_planes; s.n_lights = n_lights;
     s.spec_model = spec_model;

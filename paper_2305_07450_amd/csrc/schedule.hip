@@ -16,7 +16,8 @@
 //
 // The render that records also counts its tiles per chunk of 1024 and bin
 // (render.hip).  One launch here: blocks [0, cone_blocks) write the eye cones
-// (the arithmetic of eye_cone_kernel, so the same bits) and zero the
+// and eye - centre table (the arithmetic of eye_cone_kernel, so the same
+// bits) and zero the
 // histograms the coming render fills; each block of [cone_blocks,
 // cone_blocks + chunks) places the 1024 tiles of its chunk in the order,
 // longest bin first and row order within a bin: from the chunk histograms it
@@ -34,6 +35,7 @@ struct PrepareArgs {
   const float4* geom;       // [n4 + kGroup] centre, r^2
   const float2* rad;        // [N] r, 1/r
   float4* eye_cone;         // [n4 + kGroup] out
+  float4* eye_oc;           // [n4 + kGroup] out: eye - centre, r^2
   int n_spheres;
   int cone_blocks, chunks;
   float ex, ey, ez;         // the eye
@@ -54,8 +56,10 @@ __global__ __launch_bounds__(kPrepThreads) void prepare_kernel(PrepareArgs a) {
     if (i < a.n_spheres) {
       const float4 g = a.geom[i];
       a.eye_cone[i] = sphere_cone(a.ex, a.ey, a.ez, g.x, g.y, g.z, a.rad[i].x);
+      a.eye_oc[i] = make_float4(a.ex - g.x, a.ey - g.y, a.ez - g.z, g.w);
     } else if (i < pad_spheres(a.n_spheres) + kGroup) {
       a.eye_cone[i] = make_float4(0.0f, 0.0f, 0.0f, kPadConeW);
+      a.eye_oc[i] = make_float4(0.0f, 0.0f, 0.0f, kPadR2);
     }
     if (b == 0 && a.next_hist)
       for (int j = tid; j < kSchedChunks * kSchedBins; j += kPrepThreads) a.next_hist[j] = 0;
@@ -128,6 +132,7 @@ hipError_t launch_prepare(rt_scene_s& sc, const CameraDev& c, bool schedule, int
   a.geom = sc.geom;
   a.rad = sc.rad;
   a.eye_cone = sc.eye_cone;
+  a.eye_oc = sc.eye_oc;
   a.n_spheres = sc.n_spheres;
   a.ex = c.ex;
   a.ey = c.ey;

@@ -37,6 +37,14 @@ struct SceneDev {
   const float4* light;   // [L]   position, intensity
   const float4* eye_cone;    // [N]    cone of each sphere seen from the eye
   const float4* light_cone;  // [L][N] cone of each sphere seen from each light
+  // o - c and r^2 of each sphere for the rays that share an origin: the eye
+  // (primary rays) and each light (shadow rays, traced reversed from it).
+  // Each is the FP32 difference the per-lane code would form, so a test that
+  // reads it gives the same bits.  The scans and candidate loops read them
+  // with scalar loads, which saves the three subtractions (and the moves that
+  // feed their scalar operands) per sphere and lane.
+  const float4* eye_oc;      // [N]    eye - centre, r^2 (padding: r^2 = -1)
+  const float4* light_oc;    // [L][N] light - centre, r^2
   int n_spheres, n_planes, n_lights, spec_model;
   int n4;   // sphere tables padded to a multiple of kGroup (+kGroup for prefetch)
   float ambient, spec_strength, t_min;
@@ -570,7 +578,7 @@ __device__ __forceinline__ bool sphere_may_meet(const WaveBundle& b, float4 g, f
 // ray costs about kTransHitCost VALU operations in the closest-hit search and
 // kTransShadowCost in a shadow test, against about kLaneHitCost and
 // kLaneShadowCost per candidate sphere in the per-lane loops.
-constexpr int kTransHitCost = 45, kLaneHitCost = 20;
+constexpr int kTransHitCost = 60, kLaneHitCost = 20;
 constexpr int kTransShadowCost = 20, kLaneShadowCost = 10;
 constexpr bool kTransposedHit = true, kTransposedShadow = true;
 
@@ -663,18 +671,17 @@ __device__ __forceinline__ void closest_hit(const SceneDev& s, const Ray& r, boo
         const int j = base + lane;
         const int jc = j < s.n_spheres ? j : s.n_spheres - 1;
         const float4 a = s.eye_cone[jc];
-        const float4 g = s.geom[jc];
-        // every lane's ray starts at the eye: o - c of this lane's sphere is
-        // the o - c every lane would form for it
-        const float ocx = r.ox - g.x, ocy = r.oy - g.y, ocz = r.oz - g.z;
         uint64_t m = wave_mask((j < s.n_spheres) & cone_may_pass(wc, a));
         while (m) {
-          const int k = (int)__builtin_ctzll(m);
+          // candidate i: its cone, then (every lane's ray starting at the
+          // eye) its o - c, through scalar loads (issue slots of the scalar
+          // memory unit, not of the VALU, which bounds this kernel)
+          const int i = base + (int)__builtin_ctzll(m);
           m &= m - 1;
-          if (wave_any(live & (cone_excess(lane_read4(a, k), r.dx, r.dy, r.dz) >= 0.0f))) {
+          if (wave_any(live & (cone_excess(ld4(s.eye_cone, i), r.dx, r.dy, r.dz) >= 0.0f))) {
             cnt.exec(live ? 1 : 0, 0);
-            test_sphere_oc(lane_read(ocx, k), lane_read(ocy, k), lane_read(ocz, k),
-                           lane_read(g.w, k), base + k, r, tmin, t_best, id_best);
+            const float4 oc = ld4(s.eye_oc, i);
+            test_sphere_oc(oc.x, oc.y, oc.z, oc.w, i, r, tmin, t_best, id_best);
           }
         }
       }
@@ -684,7 +691,8 @@ __device__ __forceinline__ void closest_hit(const SceneDev& s, const Ray& r, boo
           [&](int i, float4 a) {
             if (wave_any(live & (cone_excess(a, r.dx, r.dy, r.dz) >= 0.0f))) {
               cnt.exec(live ? 1 : 0, 0);
-              test_sphere(ld4(s.geom, i), i, r, tmin, t_best, id_best);
+              const float4 oc = ld4(s.eye_oc, i);
+              test_sphere_oc(oc.x, oc.y, oc.z, oc.w, i, r, tmin, t_best, id_best);
             }
           },
           [] { return false; });
@@ -710,9 +718,9 @@ __device__ __forceinline__ void closest_hit(const SceneDev& s, const Ray& r, boo
         } else if (wb.on) {
           cnt.exec(live ? __builtin_popcountll(m) : 0, 0);
           while (m) {
-            const int k = (int)__builtin_ctzll(m);
+            const int i = base + (int)__builtin_ctzll(m);
             m &= m - 1;
-            test_sphere(lane_read4(g, k), base + k, r, tmin, t_best, id_best);
+            test_sphere(ld4(s.geom, i), i, r, tmin, t_best, id_best);   // scalar load
           }
         } else {
           cnt.exec(live ? min(64, s.n_spheres - base) : 0, 0);
@@ -722,6 +730,13 @@ __device__ __forceinline__ void closest_hit(const SceneDev& s, const Ray& r, boo
               [] { return false; });
         }
       }
+    } else if (kFromEye) {
+      // every ray starts at the eye: o - c and r^2 from the scene's table
+      cnt.exec(live ? s.n_spheres : 0, 0);
+      scan_spheres(
+          s.eye_oc, s.n4,
+          [&](int i, float4 a) { test_sphere_oc(a.x, a.y, a.z, a.w, i, r, tmin, t_best, id_best); },
+          [] { return false; });
     } else {
       cnt.exec(live ? s.n_spheres : 0, 0);
       scan_spheres(
@@ -791,6 +806,7 @@ __device__ __forceinline__ bool occluded(const SceneDev& s, int l, float4 q, con
   const float lim = dist - s.t_min;
   const float ux = -lx, uy = -ly, uz = -lz;
   const float4* cones = s.light_cone + (int64_t)l * s.n4;
+  const float4* ocs = s.light_oc + (int64_t)l * s.n4;
   const int self = f.id;
   bool occ = !act;
   int first = 0;   // first occluding sphere, for the work counters
@@ -807,17 +823,16 @@ __device__ __forceinline__ bool occluded(const SceneDev& s, int l, float4 q, con
       const int j = base + lane;
       const int jc = j < s.n_spheres ? j : s.n_spheres - 1;
       const float4 a = cones[jc];
-      const float4 g = s.geom[jc];
-      // every reversed shadow ray starts at the light (see closest_hit)
-      const float ocx = q.x - g.x, ocy = q.y - g.y, ocz = q.z - g.z;
       uint64_t m = wave_mask((j < s.n_spheres) & cone_may_pass(wc, a));
       while (m) {
-        const int k = (int)__builtin_ctzll(m);
+        // candidate i: its cone and (every reversed shadow ray starting at
+        // the light) its o - c, through scalar loads (see closest_hit)
+        const int i = base + (int)__builtin_ctzll(m);
         m &= m - 1;
-        if (wave_any(!occ & (cone_excess(lane_read4(a, k), ux, uy, uz) >= 0.0f))) {
+        if (wave_any(!occ & (cone_excess(ld4(cones, i), ux, uy, uz) >= 0.0f))) {
           cnt.exec(occ ? 0 : 1, 0);
-          shadow_sphere_oc(lane_read(ocx, k), lane_read(ocy, k), lane_read(ocz, k),
-                           lane_read(g.w, k), base + k, rr, lim, self, occ, first);
+          const float4 oc = ld4(ocs, i);
+          shadow_sphere_oc(oc.x, oc.y, oc.z, oc.w, i, rr, lim, self, occ, first);
           if (!wave_any(!occ)) {   // every lane of the wave is occluded
             done = true;
             break;
@@ -835,9 +850,9 @@ __device__ __forceinline__ bool occluded(const SceneDev& s, int l, float4 q, con
       const int j = base + lane;
       const int jc = j < s.n_spheres ? j : s.n_spheres - 1;
       const float4 a = cones[jc];
-      const float4 g = s.geom[jc];
-      // every reversed shadow ray starts at the light (see closest_hit)
-      const float ocx = q.x - g.x, ocy = q.y - g.y, ocz = q.z - g.z;
+      // every reversed shadow ray starts at the light: this lane's sphere's
+      // o - c and r^2, for the transposed test
+      const float4 oc = ocs[jc];
       bool cand = j < s.n_spheres;
       if (wc.on) cand = cand & cone_may_pass(wc, a);
       uint64_t m = wave_mask(cand);
@@ -847,16 +862,16 @@ __device__ __forceinline__ bool occluded(const SceneDev& s, int l, float4 q, con
         // every ray not yet blocked meets every candidate (the transposed
         // loop does not stop a ray at its first occluder within the chunk)
         cnt.exec(occ ? 0 : __builtin_popcountll(m), 0);
-        transposed_shadow(ocx, ocy, ocz, g.w, m, base, rr, lim, self, occ, first);
+        transposed_shadow(oc.x, oc.y, oc.z, oc.w, m, base, rr, lim, self, occ, first);
         done = !wave_any(!occ);
       } else if (wc.on) {
         while (m) {
-          const int k = (int)__builtin_ctzll(m);
+          const int i = base + (int)__builtin_ctzll(m);
           m &= m - 1;
-          if (wave_any(!occ & (cone_excess(lane_read4(a, k), ux, uy, uz) >= 0.0f))) {
+          if (wave_any(!occ & (cone_excess(ld4(cones, i), ux, uy, uz) >= 0.0f))) {
             cnt.exec(occ ? 0 : 1, 0);
-            shadow_sphere_oc(lane_read(ocx, k), lane_read(ocy, k), lane_read(ocz, k),
-                             lane_read(g.w, k), base + k, rr, lim, self, occ, first);
+            const float4 oc = ld4(ocs, i);
+            shadow_sphere_oc(oc.x, oc.y, oc.z, oc.w, i, rr, lim, self, occ, first);
             if (!wave_any(!occ)) {   // every lane of the wave is occluded
               done = true;
               break;
@@ -869,20 +884,32 @@ __device__ __forceinline__ bool occluded(const SceneDev& s, int l, float4 q, con
             [&](int i, float4 ai) {
               if (wave_any(!occ & (cone_excess(ai, ux, uy, uz) >= 0.0f))) {
                 cnt.exec(occ ? 0 : 1, 0);
-                shadow_sphere(ld4(s.geom, i), i, rr, lim, self, occ, first);
+                const float4 oc = ld4(ocs, i);
+                shadow_sphere_oc(oc.x, oc.y, oc.z, oc.w, i, rr, lim, self, occ, first);
               }
             },
             [&] { return !wave_any(!occ); });
         done = !wave_any(!occ);
       }
     }
+  } else if (!kPrefilter) {
+    // every reversed shadow ray starts at the light: o - c and r^2 from the
+    // scene's table
+    scan_spheres(
+        ocs, s.n4,
+        [&](int i, float4 a) {
+          cnt.exec((occ || i >= s.n_spheres) ? 0 : 1, 0);   // padding spheres are no work
+          shadow_sphere_oc(a.x, a.y, a.z, a.w, i, rr, lim, self, occ, first);
+        },
+        [&] { return !wave_any(!occ); });   // every lane of the wave is occluded
   } else {
     scan_spheres(
         cones, s.n4,
         [&](int i, float4 a) {
-          if (!kPrefilter || wave_any(!occ & (cone_excess(a, ux, uy, uz) >= 0.0f))) {
+          if (wave_any(!occ & (cone_excess(a, ux, uy, uz) >= 0.0f))) {
             cnt.exec((occ || i >= s.n_spheres) ? 0 : 1, 0);   // padding spheres are no work
-            shadow_sphere(ld4(s.geom, i), i, rr, lim, self, occ, first);
+            const float4 oc = ld4(ocs, i);
+            shadow_sphere_oc(oc.x, oc.y, oc.z, oc.w, i, rr, lim, self, occ, first);
           }
         },
         [&] { return !wave_any(!occ); });   // every lane of the wave is occluded
