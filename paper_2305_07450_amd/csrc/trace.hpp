@@ -279,10 +279,14 @@ __device__ __forceinline__ float4 lane_read4(float4 v, int lane) {
   return make_float4(lane_read(v.x, lane), lane_read(v.y, lane), lane_read(v.z, lane),
                      lane_read(v.w, lane));
 }
-// Minimum over all 64 lanes (all executing), in every lane.  The floats are
-// mapped to integers of the same order (the magnitude bits of negatives
-// flipped), so each step is one integer min with a DPP operand: quad swaps,
-// half-row and row mirrors within each row of 16, then the four row results.
+// Minimum over all 64 lanes (all executing), as a wave-uniform value.  The
+// floats are mapped to integers of the same order (the magnitude bits of
+// negatives flipped), so each step is one integer min with a DPP operand:
+// quad swaps, half-row and row mirrors within each row of 16, then the row
+// broadcasts of lanes 15 and 31, after which lane 63 holds the minimum of all
+// four rows (lanes of the first rows hold partial or out-of-row values that
+// are not read).  Seven VALU instructions; four readlanes of the row results
+// took eight.
 __device__ __forceinline__ int float_order(float v) {
   const int i = __builtin_bit_cast(int, v);
   return i ^ ((i >> 31) & 0x7fffffff);
@@ -299,10 +303,10 @@ __device__ __forceinline__ float wave_min(float x) {
   v = dpp_min<0xB1>(v);    // quad_perm [1, 0, 3, 2]
   v = dpp_min<0x4E>(v);    // quad_perm [2, 3, 0, 1]
   v = dpp_min<0x141>(v);   // row_half_mirror
-  v = dpp_min<0x140>(v);   // row_mirror
-  const int a = min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16));
-  const int b = min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48));
-  return order_float(min(a, b));
+  v = dpp_min<0x140>(v);   // row_mirror: every lane holds its row's minimum
+  v = dpp_min<0x142>(v);   // row_bcast:15: lane 63 holds the minimum of rows 2 and 3
+  v = dpp_min<0x143>(v);   // row_bcast:31: and of rows 0 and 1
+  return order_float(__builtin_amdgcn_readlane(v, 63));
 }
 
 // Exact test of sphere i against the ray, given oc = o - c and r^2; keeps
@@ -578,8 +582,8 @@ __device__ __forceinline__ bool sphere_may_meet(const WaveBundle& b, float4 g, f
 // ray costs about kTransHitCost VALU operations in the closest-hit search and
 // kTransShadowCost in a shadow test, against about kLaneHitCost and
 // kLaneShadowCost per candidate sphere in the per-lane loops.
-constexpr int kTransHitCost = 60, kLaneHitCost = 20;
-constexpr int kTransShadowCost = 20, kLaneShadowCost = 10;
+constexpr int kTransHitCost = 75, kLaneHitCost = 20;
+constexpr int kTransShadowCost = 25, kLaneShadowCost = 10;
 constexpr bool kTransposedHit = true, kTransposedShadow = true;
 
 // Nearest root over the spheres base + j (j in `cand`, geometry g in lane j)
