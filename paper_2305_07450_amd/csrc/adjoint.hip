@@ -34,7 +34,9 @@ constexpr int kLdsFloats = 16384;  // 64 KiB: accumulator budget per workgroup w
 // Sum over the 64 lanes in a fixed order, so that runs repeat bit for bit.
 // With every lane executing: DPP adds within each row of 16 (quad swaps, half
 // mirror, mirror; both lanes of a pair add the same two values, so a row ends
-// with one value), then the four rows in a fixed order.  Otherwise an xor
+// with one value R_r), then the row broadcasts of lanes 15 and 31, which
+// leave (R3 + R2) + (R1 + R0) in lane 63 (lanes of the first rows hold
+// partial or out-of-row values that are not read).  Otherwise an xor
 // butterfly through the LDS crossbar.  Every lane gets the sum.
 template <int kCtrl>
 __device__ __forceinline__ float dpp_add(float v) {
@@ -47,11 +49,40 @@ __device__ __forceinline__ float wave_sum(float v) {
     v = dpp_add<0x4E>(v);    // quad_perm [2, 3, 0, 1]
     v = dpp_add<0x141>(v);   // row_half_mirror
     v = dpp_add<0x140>(v);   // row_mirror
-    return (lane_read(v, 0) + lane_read(v, 16)) + (lane_read(v, 32) + lane_read(v, 48));
+    v = dpp_add<0x142>(v);   // row_bcast:15
+    v = dpp_add<0x143>(v);   // row_bcast:31
+    return lane_read(v, 63);
   }
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
+}
+
+// wave_sum of kN values at once, each in the same steps and order as
+// wave_sum (so the same bits), with the kN chains of dependent DPP steps
+// interleaved step by step so that each step's latency is hidden behind the
+// other values' steps.
+template <int kN>
+__device__ __forceinline__ void wave_sums(float (&v)[kN]) {
+  if (wave_full()) {
+#pragma unroll
+    for (int j = 0; j < kN; ++j) v[j] = dpp_add<0xB1>(v[j]);
+#pragma unroll
+    for (int j = 0; j < kN; ++j) v[j] = dpp_add<0x4E>(v[j]);
+#pragma unroll
+    for (int j = 0; j < kN; ++j) v[j] = dpp_add<0x141>(v[j]);
+#pragma unroll
+    for (int j = 0; j < kN; ++j) v[j] = dpp_add<0x140>(v[j]);
+#pragma unroll
+    for (int j = 0; j < kN; ++j) v[j] = dpp_add<0x142>(v[j]);
+#pragma unroll
+    for (int j = 0; j < kN; ++j) v[j] = dpp_add<0x143>(v[j]);
+#pragma unroll
+    for (int j = 0; j < kN; ++j) v[j] = lane_read(v[j], 63);
+    return;
+  }
+#pragma unroll
+  for (int j = 0; j < kN; ++j) v[j] = wave_sum(v[j]);
 }
 
 // Light terms with a fixed lit mask (no shadow rays): the same arithmetic
@@ -415,12 +446,12 @@ __global__ __launch_bounds__(256) void adjoint_kernel(SceneDev s, CameraDev c, i
           const int leader = __builtin_ctzll(pending);
           const int key = __builtin_amdgcn_readlane(sid, leader);
           const bool mine = sid == key;
-          float v[7] = {sa0, sa1, sa2, skr, sc0, sc1, sc2};
+          float v[7] = {mine ? sa0 : 0.f, mine ? sa1 : 0.f, mine ? sa2 : 0.f, mine ? skr : 0.f,
+                        mine ? sc0 : 0.f, mine ? sc1 : 0.f, mine ? sc2 : 0.f};
+          wave_sums(v);
 #pragma unroll
-          for (int j = 0; j < 7; ++j) {
-            float tot = wave_sum(mine ? v[j] : 0.0f);
-            if (lane == 0) my_acc[7 * key + j] += tot;
-          }
+          for (int j = 0; j < 7; ++j)
+            if (lane == 0) my_acc[7 * key + j] += v[j];
           pending &= ~__ballot(mine);
         }
       }
