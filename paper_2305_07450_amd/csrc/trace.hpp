@@ -275,10 +275,6 @@ __device__ __forceinline__ bool wave_full() { return __builtin_amdgcn_read_exec(
 __device__ __forceinline__ float lane_read(float v, int lane) {
   return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
 }
-__device__ __forceinline__ float4 lane_read4(float4 v, int lane) {
-  return make_float4(lane_read(v.x, lane), lane_read(v.y, lane), lane_read(v.z, lane),
-                     lane_read(v.w, lane));
-}
 // Minimum over all 64 lanes (all executing), as a wave-uniform value.  The
 // floats are mapped to integers of the same order (the magnitude bits of
 // negatives flipped), so each step is one integer min with a DPP operand:
@@ -1136,6 +1132,9 @@ __device__ __forceinline__ float soft_visibility(const SceneDev& s, float4 q, co
     }
   }
   int visible = 0;
+  // the light centre relative to p, formed once: a sample ray's direction is
+  // q - p plus the sample's offset in the disk
+  const float qpx = q.x - f.px, qpy = q.y - f.py, qpz = q.z - f.pz;
   // the table is read 8 samples (64 bytes) per scalar load; it holds a
   // multiple of 8 entries, so the last block stays inside it (entries past n
   // are read but count as blocked)
@@ -1151,9 +1150,9 @@ __device__ __forceinline__ float soft_visibility(const SceneDev& s, float4 q, co
       for (int k = 0; k < kSoftGroup; ++k) {
         const int kk = k0 + k;
         const float u = tb[2 * kk], v = tb[2 * kk + 1];   // already times the radius
-        float x = fmaf(u, ax, fmaf(v, bx, q.x)) - f.px;
-        float y = fmaf(u, ay, fmaf(v, by, q.y)) - f.py;
-        float z = fmaf(u, az, fmaf(v, bz, q.z)) - f.pz;
+        float x = fmaf(u, ax, fmaf(v, bx, qpx));
+        float y = fmaf(u, ay, fmaf(v, by, qpy));
+        float z = fmaf(u, az, fmaf(v, bz, qpz));
         const float d2 = dot3(x, y, z, x, y, z);
         const float inv = frsq(d2);
         di[k] = d2 * inv;
