@@ -79,8 +79,10 @@ __global__ __launch_bounds__(kRenderThreads) void render_kernel(SceneDev s, Came
   int prim;
   if (kRecords) {
     RecordSink sink{rec_ids, rec_lit, (int64_t)c.W * c.H, pix};
-    int traced = trace_path<RecordSink, NoCount, kPrefilter, HardShadows, Bg>(s, r, depth, live, cr,
-                                                                              cg, cb, prim, sink);
+    // the records' pointers leave no VGPRs for the LDS ray slots of the
+    // transposed tests (82 against 76, 5 waves per SIMD instead of 6)
+    int traced = trace_path<RecordSink, NoCount, kPrefilter, HardShadows, Bg, false>(
+        s, r, depth, live, cr, cg, cb, prim, sink);
     if (live) {
       for (int k = traced; k <= depth; ++k) {
         rec_ids[k * sink.plane + pix] = kNotTraced;
@@ -89,8 +91,8 @@ __global__ __launch_bounds__(kRenderThreads) void render_kernel(SceneDev s, Came
     }
   } else {
     NoRecords sink;
-    trace_path<NoRecords, NoCount, kPrefilter, HardShadows, Bg>(s, r, depth, live, cr, cg, cb, prim,
-                                                                sink);
+    trace_path<NoRecords, NoCount, kPrefilter, HardShadows, Bg, true>(s, r, depth, live, cr, cg, cb,
+                                                                      prim, sink);
   }
   if (live) {
     rgb[3 * pix + 0] = cr;
@@ -103,7 +105,7 @@ __global__ __launch_bounds__(kRenderThreads) void render_kernel(SceneDev s, Came
 
 // Soft-shadow render: the same paths with every light sampled (SoftShadows).
 template <bool kPrefilter, class Bg>
-__global__ __launch_bounds__(kRenderThreads) void render_soft_kernel(SceneDev s, CameraDev c, int depth,
+__global__ __launch_bounds__(kRenderThreads, 4) void render_soft_kernel(SceneDev s, CameraDev c, int depth,
                                                            SoftShadows sh,
                                                            float* __restrict__ rgb,
                                                            int32_t* __restrict__ id_out) {
@@ -123,8 +125,9 @@ __global__ __launch_bounds__(kRenderThreads) void render_soft_kernel(SceneDev s,
   float cr, cg, cb;
   int prim;
   NoRecords sink;
-  trace_path<NoRecords, NoCount, kPrefilter, SoftShadows, Bg>(s, r, depth, live, cr, cg, cb, prim,
-                                                              sink, NoCount(), sh);
+  // no LDS ray slots: they cost the skybox variant a wave per SIMD (129 VGPRs)
+  trace_path<NoRecords, NoCount, kPrefilter, SoftShadows, Bg, false>(s, r, depth, live, cr, cg, cb,
+                                                                       prim, sink, NoCount(), sh);
   if (live) {
     rgb[3 * pix + 0] = cr;
     rgb[3 * pix + 1] = cg;

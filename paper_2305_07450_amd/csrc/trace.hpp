@@ -585,17 +585,33 @@ constexpr bool kTransposedHit = true, kTransposedShadow = true;
 // Nearest root over the spheres base + j (j in `cand`, geometry g in lane j)
 // for every ray of `rays`; strict < against each ray's running best, and the
 // lowest id among equal roots, as the ascending per-lane scan gives.
+//
+// kLds (kernels whose workgroup is one wave): ray q comes from per-lane LDS
+// slots, one broadcast read (no bank conflicts) instead of six readlanes, each
+// of which takes a VALU issue slot; a wave reads its own LDS writes in order.
+template <bool kLds>
 __device__ __forceinline__ void transposed_hit(float4 g, uint64_t cand, int base, uint64_t rays,
                                                const Ray& r, float tmin, float& t_best,
                                                int& id_best) {
   const int lane = __lane_id();
   const bool mine = (cand >> lane) & 1u;
+  __shared__ float4 s_ro[kLds ? 64 : 1], s_rd[kLds ? 64 : 1];
+  if constexpr (kLds) {
+    s_ro[lane] = make_float4(r.ox, r.oy, r.oz, 0.0f);
+    s_rd[lane] = make_float4(r.dx, r.dy, r.dz, 0.0f);
+  }
   while (rays) {
     const int q = (int)__builtin_ctzll(rays);
     rays &= rays - 1;
     Ray rq;
-    rq.ox = lane_read(r.ox, q); rq.oy = lane_read(r.oy, q); rq.oz = lane_read(r.oz, q);
-    rq.dx = lane_read(r.dx, q); rq.dy = lane_read(r.dy, q); rq.dz = lane_read(r.dz, q);
+    if constexpr (kLds) {
+      const float4 o4 = s_ro[q], d4 = s_rd[q];
+      rq.ox = o4.x; rq.oy = o4.y; rq.oz = o4.z;
+      rq.dx = d4.x; rq.dy = d4.y; rq.dz = d4.z;
+    } else {
+      rq.ox = lane_read(r.ox, q); rq.oy = lane_read(r.oy, q); rq.oz = lane_read(r.oz, q);
+      rq.dx = lane_read(r.dx, q); rq.dy = lane_read(r.dy, q); rq.dz = lane_read(r.dz, q);
+    }
     float b;
     const float ff = sphere_ff(g, rq, b);
     const bool in = mine & (ff <= g.w);
@@ -612,20 +628,37 @@ __device__ __forceinline__ void transposed_hit(float4 g, uint64_t cand, int base
 
 // Shadow occlusion of every not yet occluded lane by the spheres base + j
 // (j in `cand`; o - c and r^2 of the reversed ray in lane j); records the
-// first occluder, as the ascending per-lane scan does.
+// first occluder, as the ascending per-lane scan does.  kLds: as in
+// transposed_hit, for the direction, limit and surface of ray q.
+template <bool kLds>
 __device__ __forceinline__ void transposed_shadow(float ocx, float ocy, float ocz, float r2,
                                                   uint64_t cand, int base, const Ray& rr,
                                                   float lim, int self, bool& occ, int& first) {
   const int lane = __lane_id();
   const bool mine = (cand >> lane) & 1u;
   uint64_t rays = wave_mask(!occ);
+  __shared__ float4 s_sd[kLds ? 64 : 1];
+  __shared__ int s_self[kLds ? 64 : 1];
+  if constexpr (kLds) {
+    s_sd[lane] = make_float4(rr.dx, rr.dy, rr.dz, lim);
+    s_self[lane] = self;
+  }
   while (rays) {
     const int q = (int)__builtin_ctzll(rays);
     rays &= rays - 1;
     Ray rq = rr;   // the origin is the light for every lane
-    rq.dx = lane_read(rr.dx, q); rq.dy = lane_read(rr.dy, q); rq.dz = lane_read(rr.dz, q);
-    const float limq = lane_read(lim, q);
-    const int selfq = __builtin_amdgcn_readlane(self, q);
+    float limq;
+    int selfq;
+    if constexpr (kLds) {
+      const float4 d4 = s_sd[q];
+      rq.dx = d4.x; rq.dy = d4.y; rq.dz = d4.z;
+      limq = d4.w;
+      selfq = s_self[q];
+    } else {
+      rq.dx = lane_read(rr.dx, q); rq.dy = lane_read(rr.dy, q); rq.dz = lane_read(rr.dz, q);
+      limq = lane_read(lim, q);
+      selfq = __builtin_amdgcn_readlane(self, q);
+    }
     float b;
     const float ff = sphere_ff_oc(ocx, ocy, ocz, rq, b);
     const bool in = mine & (ff <= r2) & (base + lane != selfq);
@@ -656,7 +689,7 @@ __device__ __forceinline__ void transposed_shadow(float ocx, float ocy, float oc
 // bounded by a wave bundle, and only the spheres it may meet run the exact
 // test.  Skipped spheres are ones the exact test would reject, and the exact
 // test is the same code in every path, so all paths give the same bits.
-template <bool kFromEye, bool kPrefilter, class Cnt>
+template <bool kFromEye, bool kPrefilter, class Cnt, bool kLds = false>
 __device__ __forceinline__ void closest_hit(const SceneDev& s, const Ray& r, bool live,
                                             float& t_best, int& id_best, Cnt& cnt,
                                             int from_plane = -1) {
@@ -714,7 +747,7 @@ __device__ __forceinline__ void closest_hit(const SceneDev& s, const Ray& r, boo
         uint64_t m = wave_mask(cand);
         if (kTransposedHit && n_rays * kTransHitCost < __builtin_popcountll(m) * kLaneHitCost) {
           cnt.exec(live ? __builtin_popcountll(m) : 0, 0);
-          transposed_hit(g, m, base, rays, r, tmin, t_best, id_best);
+          transposed_hit<kLds>(g, m, base, rays, r, tmin, t_best, id_best);
         } else if (wb.on) {
           cnt.exec(live ? __builtin_popcountll(m) : 0, 0);
           while (m) {
@@ -799,7 +832,7 @@ __device__ __forceinline__ void shadow_sphere(float4 g, int i, const Ray& rr, fl
 // n.l > 0, i.e. it leaves that convex surface outwards and cannot meet it
 // again, so its test is skipped: in exact arithmetic it never occludes, and
 // skipping it keeps FP32 rounding of p from re-hitting it.
-template <bool kPrefilter, bool kDense, class Cnt>
+template <bool kPrefilter, bool kDense, class Cnt, bool kLds = false>
 __device__ __forceinline__ bool occluded(const SceneDev& s, int l, float4 q, const Surface& f,
                                          float lx, float ly, float lz, float dist, bool act,
                                          Cnt& cnt) {
@@ -862,7 +895,7 @@ __device__ __forceinline__ bool occluded(const SceneDev& s, int l, float4 q, con
         // every ray not yet blocked meets every candidate (the transposed
         // loop does not stop a ray at its first occluder within the chunk)
         cnt.exec(occ ? 0 : __builtin_popcountll(m), 0);
-        transposed_shadow(oc.x, oc.y, oc.z, oc.w, m, base, rr, lim, self, occ, first);
+        transposed_shadow<kLds>(oc.x, oc.y, oc.z, oc.w, m, base, rr, lim, self, occ, first);
         done = !wave_any(!occ);
       } else if (wc.on) {
         while (m) {
@@ -1204,7 +1237,7 @@ __device__ __forceinline__ float soft_visibility(const SceneDev& s, float4 q, co
 // Only lanes with `on` take part (the others get a mask of 0); the shadow
 // rays of a light are traced while any lane of the wave needs one.
 template <bool kPrefilter = true, bool kDense = false, class Cnt = NoCount,
-          class Shadows = HardShadows>
+          class Shadows = HardShadows, bool kLds = false>
 __device__ __forceinline__ uint32_t light_terms(const SceneDev& s, const Surface& f, const Ray& r,
                                                 bool on, float& A, float& S, Cnt& cnt,
                                                 const Shadows& sh = Shadows()) {
@@ -1236,7 +1269,8 @@ __device__ __forceinline__ uint32_t light_terms(const SceneDev& s, const Surface
         }
       } else {
         if (act) cnt.ray(kCntShadow);
-        const bool occ = occluded<kPrefilter, kDense>(s, l, q, f, lx, ly, lz, dist, act, cnt);
+        const bool occ =
+            occluded<kPrefilter, kDense, Cnt, kLds>(s, l, q, f, lx, ly, lz, dist, act, cnt);
         if (act && !occ) {
           lit |= 1u << l;
           A = fmaf(q.w, nl, A);
@@ -1340,16 +1374,16 @@ struct PathState {
 // `sink.seg(k, id)` / `sink.lit(k, mask)` see the segment.  Every kernel runs
 // a segment through this one function, with all lanes of the wave executing.
 template <bool kFromEye, bool kPrefilter, class Sink, class Cnt, class Shadows = HardShadows,
-          class Bg = PlainBackground>
+          class Bg = PlainBackground, bool kLds = false>
 __device__ __forceinline__ int trace_segment(const SceneDev& s, PathState& ps, int k, int depth,
                                              bool& alive, Sink& sink, Cnt& cnt,
                                              const Shadows& sh = Shadows()) {
   float t;
   int id;
   if (kFromEye)
-    closest_hit<true, kPrefilter>(s, ps.r, alive, t, id, cnt);
+    closest_hit<true, kPrefilter, Cnt, kLds>(s, ps.r, alive, t, id, cnt);
   else
-    closest_hit<false, kPrefilter>(s, ps.r, alive, t, id, cnt, ps.from_plane);
+    closest_hit<false, kPrefilter, Cnt, kLds>(s, ps.r, alive, t, id, cnt, ps.from_plane);
   if (alive) {
     cnt.ray(k == 0 ? kCntPrimary : kCntReflection);
     cnt.tests(s.n_spheres, s.n_planes);
@@ -1368,7 +1402,8 @@ __device__ __forceinline__ int trace_segment(const SceneDev& s, PathState& ps, i
     // lanes without a hit shade primitive 0 along and keep nothing of it
     Surface f = surface_geom(s, ps.r, t, hit ? id : 0);
     float A, S;
-    const uint32_t lit = light_terms<kPrefilter, kFromEye>(s, f, ps.r, hit, A, S, cnt, sh);
+    const uint32_t lit =
+        light_terms<kPrefilter, kFromEye, Cnt, Shadows, kLds>(s, f, ps.r, hit, A, S, cnt, sh);
     const float4 mat = ld4(s.mat, f.id);
     f.ar = mat.x; f.ag = mat.y; f.ab = mat.z; f.kr = mat.w;
     if (hit) {
@@ -1397,7 +1432,7 @@ __device__ __forceinline__ int trace_segment(const SceneDev& s, PathState& ps, i
 // `sink.lit(k, mask)` see every traced segment; the caller marks untraced
 // segments.  Returns the number of segments traced (0 when not live).
 template <class Sink, class Cnt = NoCount, bool kPrefilter = true, class Shadows = HardShadows,
-          class Bg = PlainBackground>
+          class Bg = PlainBackground, bool kLds = false>
 __device__ __forceinline__ int trace_path(const SceneDev& s, Ray r, int depth, bool live,
                                           float& cr, float& cg, float& cb, int& prim, Sink& sink,
                                           Cnt&& cnt = Cnt(), const Shadows& sh = Shadows()) {
@@ -1407,14 +1442,14 @@ __device__ __forceinline__ int trace_path(const SceneDev& s, Ray r, int depth, b
   ps.cr = 0.0f; ps.cg = 0.0f; ps.cb = 0.0f;
   ps.from_plane = -1;
   bool alive = live;
-  prim = trace_segment<true, kPrefilter, Sink, Cnt, Shadows, Bg>(s, ps, 0, depth, alive, sink,
-                                                                    cnt, sh);
+  prim = trace_segment<true, kPrefilter, Sink, Cnt, Shadows, Bg, kLds>(s, ps, 0, depth, alive,
+                                                                          sink, cnt, sh);
   int traced = live ? 1 : 0;
   for (int k = 1; k <= depth; ++k) {
     if (!wave_any(alive)) break;
     traced = alive ? k + 1 : traced;
-    trace_segment<false, kPrefilter, Sink, Cnt, Shadows, Bg>(s, ps, k, depth, alive, sink, cnt,
-                                                             sh);
+    trace_segment<false, kPrefilter, Sink, Cnt, Shadows, Bg, kLds>(s, ps, k, depth, alive, sink,
+                                                                   cnt, sh);
   }
   cr = ps.cr; cg = ps.cg; cb = ps.cb;
   return traced;
