@@ -3,9 +3,11 @@
 // Launch shape: one wave64 per workgroup, owning an 8 x 8 pixel tile (one lane
 // per pixel, paper Section 3.9: every pixel is an independent work item), so
 // the 64 rays of a wave start from the same eye through neighbouring pixels
-// and take the same branch over most primitives.  The kernels use no LDS, so
-// the workgroup is only a unit of dispatch: single waves fill the compute
-// units more evenly than groups of four did (5 % faster at 1080p).
+// and take the same branch over most primitives.  The workgroup is only a
+// unit of dispatch: single waves fill the compute units more evenly than
+// groups of four did (5 % faster at 1080p).  LDS holds only wave-private data
+// (the tile's start time, and in render_kernel the per-lane ray slots of the
+// transposed tests, which rely on the workgroup being this one wave).
 // The scene is read through scalar loads (trace.hpp), so the inner loops are
 // pure VALU arithmetic on SGPR operands.
 #include "rt_internal.hpp"
@@ -13,6 +15,7 @@
 namespace rtk {
 
 constexpr int kTile = kRenderTile;   // wave tile edge = workgroup tile edge
+static_assert(kRenderThreads == 64, "one wave per workgroup: the LDS ray slots are the wave's own");
 
 // Records sink: segment ids and lit masks in [depth+1][H][W] planes.
 struct RecordSink {
