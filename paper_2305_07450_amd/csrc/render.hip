@@ -55,8 +55,11 @@ __device__ __forceinline__ void record_duration(const SceneDev& s, int t, uint64
   }
 }
 
+// With records the LDS ray slots would take the kernel to 82 VGPRs (5 waves
+// per SIMD); held to 6 waves it fits them in 79 without scratch.
 template <bool kRecords, bool kPrefilter, class Bg>
-__global__ __launch_bounds__(kRenderThreads) void render_kernel(SceneDev s, CameraDev c, int depth,
+__global__ __launch_bounds__(kRenderThreads)
+__attribute__((amdgpu_waves_per_eu(kRecords ? 6 : 1))) void render_kernel(SceneDev s, CameraDev c, int depth,
                                                       float* __restrict__ rgb,
                                                       int32_t* __restrict__ id_out,
                                                       int32_t* __restrict__ rec_ids,
@@ -82,9 +85,7 @@ __global__ __launch_bounds__(kRenderThreads) void render_kernel(SceneDev s, Came
   int prim;
   if (kRecords) {
     RecordSink sink{rec_ids, rec_lit, (int64_t)c.W * c.H, pix};
-    // the records' pointers leave no VGPRs for the LDS ray slots of the
-    // transposed tests (82 against 76, 5 waves per SIMD instead of 6)
-    int traced = trace_path<RecordSink, NoCount, kPrefilter, HardShadows, Bg, false>(
+    int traced = trace_path<RecordSink, NoCount, kPrefilter, HardShadows, Bg, true>(
         s, r, depth, live, cr, cg, cb, prim, sink);
     if (live) {
       for (int k = traced; k <= depth; ++k) {
