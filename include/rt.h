@@ -290,7 +290,7 @@ rt_status rt_render_counts(rt_scene scene, const rt_camera* cam, int32_t W, int3
  * shadow occluders carry no gradient.  With rec == NULL the decisions are
  * recomputed by re-tracing; otherwise they are read from records written by
  * rt_render for the same scene, camera, size and depth.  The sum over pixels
- * is deterministic (fixed order, no floating-point atomics).  With a skybox,
+ * is deterministic (fixed order; no two lanes or waves add into one float).  With a skybox,
  * a path that ends in a miss also feeds its last mirror direction through
  * the UV mapping and the bilinear weights (texels are constants).  The
  * per-wave gradient accumulators (7 N + 4 L + 4 floats) live in LDS: up to

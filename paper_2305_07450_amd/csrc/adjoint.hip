@@ -17,9 +17,11 @@
 // and their indices are constants).
 //
 // Summation is deterministic: each wave reduces the contributions of one
-// sphere id with a fixed xor butterfly and adds them into its own LDS
-// accumulator; each workgroup then writes one partial vector, and a second
-// kernel adds the partials in a fixed order.  No floating-point atomics.
+// sphere id in a fixed order and one of its lanes adds them into the wave's
+// own LDS accumulator (an LDS add instruction with no other writer, so in
+// program order); each workgroup then writes one partial vector, and a
+// second kernel adds the partials in a fixed order.  No two lanes or waves
+// ever add into the same float.
 #include <mutex>
 #include <type_traits>
 
@@ -449,9 +451,13 @@ __global__ __launch_bounds__(256) void adjoint_kernel(SceneDev s, CameraDev c, i
           float v[7] = {mine ? sa0 : 0.f, mine ? sa1 : 0.f, mine ? sa2 : 0.f, mine ? skr : 0.f,
                         mine ? sc0 : 0.f, mine ? sc1 : 0.f, mine ? sc2 : 0.f};
           wave_sums(v);
+          // one lane adds to its wave's own accumulator, in program order:
+          // the LDS add instruction replaces a read, an add and a write,
+          // with no other writer and no change of order
+          if (lane == 0) {
 #pragma unroll
-          for (int j = 0; j < 7; ++j)
-            if (lane == 0) my_acc[7 * key + j] += v[j];
+            for (int j = 0; j < 7; ++j) atomicAdd(&my_acc[7 * key + j], v[j]);
+          }
           pending &= ~__ballot(mine);
         }
       }
