@@ -1431,6 +1431,8 @@ __device__ __forceinline__ int trace_segment(const SceneDev& s, PathState& ps, i
 // executes the segment code together.  `sink.seg(k, id)` and
 // `sink.lit(k, mask)` see every traced segment; the caller marks untraced
 // segments.  Returns the number of segments traced (0 when not live).
+// kLds: the transposed tests pass rays through LDS slots indexed by lane
+// alone, so only a kernel whose workgroup is a single wave may set it.
 template <class Sink, class Cnt = NoCount, bool kPrefilter = true, class Shadows = HardShadows,
           class Bg = PlainBackground, bool kLds = false>
 __device__ __forceinline__ int trace_path(const SceneDev& s, Ray r, int depth, bool live,
