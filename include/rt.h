@@ -176,8 +176,8 @@ int64_t rt_records_bytes(int32_t W, int32_t H, int32_t depth);
  *   id_out   device int32 [H][W] primary hit id (-1 = miss), or NULL;
  *   rec      records for rt_render_backward, or NULL.
  * Launches two kernels: the preparation, then the render.  The preparation
- * writes the cones of the spheres seen from the camera's eye into the
- * scene's own buffer.  For images of 4096 to 131072 8x8 tiles the render
+ * writes the cones of the spheres seen from the camera's eye, and their
+ * centres' offsets from the eye, into the scene's own buffer.  For images of 4096 to 131072 8x8 tiles the render
  * also records how long each of its tiles took (a byte per tile and a count
  * per duration bin, in the scene's buffer), and the preparation of the next
  * render of the scene at the same size turns that record into the order in
@@ -185,7 +185,7 @@ int64_t rt_records_bytes(int32_t W, int32_t H, int32_t depth);
  * size takes row order).  The order changes no pixel, only how well the
  * tiles fill the GPU; a record from another view or before rt_scene_update
  * is still used, as a guess.  No allocation, capture-safe.  Because the
- * eye-cone, record and order tables live in the scene, calls that write them
+ * eye-cone, eye-offset, record and order tables live in the scene, calls that write them
  * (rt_render, rt_render_ex, rt_render_prepare, rt_render_soft,
  * rt_render_counts and rt_render_backward with rec == NULL) must not overlap
  * in time for one scene: on one stream they are ordered; on different
