@@ -380,3 +380,21 @@ def test_tile_order_with_camera_inside_a_sphere_and_many_planes(rt):
         a, ia, _ = _render_flags(rt, h, wl, 0)
         b, ib, _ = _render_flags(rt, h, wl, rt.RT_RENDER_ROW_ORDER)
     assert torch.equal(a, b) and torch.equal(ia, ib)
+
+
+@pytest.mark.parametrize("W,H", [(512, 512), (504, 512), (3072, 3072)])
+def test_tile_order_at_the_limits_of_its_range(rt, W, H):
+    """The schedule's bounds: 512x512 is exactly 4096 tiles (the smallest
+    image ordered), 504x512 one column of tiles fewer (row order, no record),
+    3072x3072 147 456 tiles, past the 131 072 the order table holds (row
+    order).  Renders after the first equal the row-order render bit for bit
+    (NaN-filled outputs), with the bench scene."""
+    wl0 = scenegen.make_workload(1)
+    wl = scenegen.Workload("limits", wl0.scene, wl0.camera, W, H, 2)
+    log("case tile order limits", W, H)
+    with rt.SceneHandle(wl.scene) as h:
+        want, iw, _ = _render_flags(rt, h, wl, rt.RT_RENDER_ROW_ORDER)
+        assert not torch.isnan(want).any()
+        for k in range(3):
+            a, ia, _ = _render_flags(rt, h, wl, 0)
+            assert torch.equal(a, want) and torch.equal(ia, iw), (W, H, k)
