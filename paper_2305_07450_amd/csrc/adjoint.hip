@@ -277,6 +277,10 @@ __global__ __launch_bounds__(256) void adjoint_kernel(SceneDev s, CameraDev c, i
       // the segment after the last hit
       Ray rays[kD + 1];
       float Ts[kD + 1];
+      // each hit segment's root, kept for the reverse sweep when the path comes
+      // from records (the re-trace variant has no registers to spare: 130
+      // VGPRs would leave it 3 waves per SIMD)
+      float ts[kD + 1];
       Ray r_end;
       float T_end;
       {
@@ -288,7 +292,8 @@ __global__ __launch_bounds__(256) void adjoint_kernel(SceneDev s, CameraDev c, i
           rays[k] = r;
           Ts[k] = T;
           const int id = rr.ids[k];
-          Surface f = surface_at(s, r, root_of(s, r, id), id);
+          ts[k] = root_of(s, r, id);
+          Surface f = surface_at(s, r, ts[k], id);
           float A, S;
           light_terms_fixed(s, f, r, rr.lits[k], A, S);
           if (k < depth) {
@@ -326,7 +331,7 @@ __global__ __launch_bounds__(256) void adjoint_kernel(SceneDev s, CameraDev c, i
           const Ray r = rays[k];
           const float T = Ts[k];
           const int id = rr.ids[k];
-          const float t = root_of(s, r, id);
+          const float t = kHasRecords ? ts[k] : root_of(s, r, id);
           Surface f = surface_at(s, r, t, id);
           float A, S;
           light_terms_fixed(s, f, r, rr.lits[k], A, S);
