@@ -305,6 +305,20 @@ __device__ __forceinline__ float wave_min(float x) {
   return order_float(__builtin_amdgcn_readlane(v, 63));
 }
 
+// Keeps root t0 = -b - sq, else t1 = -b + sq (sq = sqrt(r^2 - ff)), when
+// above t_min and below t_best: sphere_root's choice, compared once.  Lanes
+// whose line misses (ff > r^2) take a NaN root, which every comparison
+// rejects, and are masked by `in` as well.
+__device__ __forceinline__ void keep_nearest(bool in, float r2, float ff, float b, float tmin,
+                                             int i, float& t_best, int& id_best) {
+  const float sq = fsqrt(r2 - ff);
+  const float t0 = -b - sq, t1 = -b + sq;
+  const float t = t0 > tmin ? t0 : t1;
+  const bool better = in & (t > tmin) & (t < t_best);
+  t_best = better ? t : t_best;
+  id_best = better ? i : id_best;
+}
+
 // Exact test of sphere i against the ray, given oc = o - c and r^2; keeps
 // the nearest.
 __device__ __forceinline__ void test_sphere_oc(float ocx, float ocy, float ocz, float r2, int i,
@@ -313,13 +327,7 @@ __device__ __forceinline__ void test_sphere_oc(float ocx, float ocy, float ocz, 
   float b;
   float ff = sphere_ff_oc(ocx, ocy, ocz, r, b);
   const bool in = ff <= r2;
-  if (wave_any(in)) {
-    // lanes that miss compute a harmless root and are masked by `better`
-    float t = sphere_root(r2, in ? ff : r2, b, tmin);
-    const bool better = in && t < t_best;
-    t_best = better ? t : t_best;
-    id_best = better ? i : id_best;
-  }
+  if (wave_any(in)) keep_nearest(in, r2, ff, b, tmin, i, t_best, id_best);
 }
 
 // Exact test of sphere i (geometry g) against the ray; keeps the nearest.
@@ -328,13 +336,7 @@ __device__ __forceinline__ void test_sphere(float4 g, int i, const Ray& r, float
   float b;
   float ff = sphere_ff(g, r, b);
   const bool in = ff <= g.w;
-  if (wave_any(in)) {
-    // lanes that miss compute a harmless root and are masked by `better`
-    float t = sphere_root(g.w, in ? ff : g.w, b, tmin);
-    const bool better = in && t < t_best;
-    t_best = better ? t : t_best;
-    id_best = better ? i : id_best;
-  }
+  if (wave_any(in)) keep_nearest(in, g.w, ff, b, tmin, i, t_best, id_best);
 }
 
 __device__ __forceinline__ float4 part(const rt_v16& v, int k) {
@@ -662,7 +664,7 @@ __device__ __forceinline__ void transposed_shadow(float ocx, float ocy, float oc
     float b;
     const float ff = sphere_ff_oc(ocx, ocy, ocz, rq, b);
     const bool in = mine & (ff <= r2) & (base + lane != selfq);
-    const float sq = fsqrt(in ? r2 - ff : 0.0f);
+    const float sq = fsqrt(r2 - ff);
     const float t0 = -b - sq, t1 = -b + sq;
     const bool hit = in & (((t0 > 0.0f) & (t0 < limq)) | ((t1 > 0.0f) & (t1 < limq)));
     const uint64_t h = wave_mask(hit);
@@ -788,7 +790,8 @@ __device__ __forceinline__ void closest_hit(const SceneDev& s, const Ray& r, boo
 }
 
 // Exact occlusion test of sphere i (geometry g) on the reversed shadow ray rr
-// for the lanes not yet occluded; records the first occluder.
+// for the lanes not yet occluded; records the first occluder.  Lanes whose
+// line misses take a NaN root and are masked by `in`.
 __device__ __forceinline__ void shadow_sphere_oc(float ocx, float ocy, float ocz, float r2, int i,
                                                  const Ray& rr, float lim, int self, bool& occ,
                                                  int& first) {
@@ -796,11 +799,31 @@ __device__ __forceinline__ void shadow_sphere_oc(float ocx, float ocy, float ocz
   float ff = sphere_ff_oc(ocx, ocy, ocz, rr, b);
   const bool in = !occ & (ff <= r2) & (i != self);
   if (wave_any(in)) {
-    float sq = fsqrt(in ? r2 - ff : 0.0f);
+    float sq = fsqrt(r2 - ff);
     float t0 = -b - sq, t1 = -b + sq;
     const bool hit = in & (((t0 > 0.0f) & (t0 < lim)) | ((t1 > 0.0f) & (t1 < lim)));
     first = hit ? i : first;
     occ = occ | hit;
+  }
+}
+// The same in a scan of every sphere that keeps `open`, the lanes not yet
+// occluded, as a wave-uniform mask: the wave takes the root test when the
+// sphere meets the line of some open lane, also when that is the sphere the
+// lane lies on (the per-lane test then skips it), so the occlusion state and
+// the surface id are read per lane only there.
+__device__ __forceinline__ void shadow_sphere_open(float ocx, float ocy, float ocz, float r2, int i,
+                                                   const Ray& rr, float lim, int self, bool& occ,
+                                                   int& first, uint64_t& open) {
+  float b;
+  const float ff = sphere_ff_oc(ocx, ocy, ocz, rr, b);
+  if (wave_mask(ff <= r2) & open) {
+    const bool in = !occ & (ff <= r2) & (i != self);
+    const float sq = fsqrt(r2 - ff);
+    const float t0 = -b - sq, t1 = -b + sq;
+    const bool hit = in & (((t0 > 0.0f) & (t0 < lim)) | ((t1 > 0.0f) & (t1 < lim)));
+    first = hit ? i : first;
+    occ = occ | hit;
+    open = wave_mask(!occ);
   }
 }
 __device__ __forceinline__ void shadow_sphere(float4 g, int i, const Ray& rr, float lim, int self,
@@ -809,7 +832,7 @@ __device__ __forceinline__ void shadow_sphere(float4 g, int i, const Ray& rr, fl
   float ff = sphere_ff(g, rr, b);
   const bool in = !occ & (ff <= g.w) & (i != self);
   if (wave_any(in)) {
-    float sq = fsqrt(in ? g.w - ff : 0.0f);
+    float sq = fsqrt(g.w - ff);
     float t0 = -b - sq, t1 = -b + sq;
     const bool hit = in & (((t0 > 0.0f) & (t0 < lim)) | ((t1 > 0.0f) & (t1 < lim)));
     first = hit ? i : first;
@@ -928,13 +951,14 @@ __device__ __forceinline__ bool occluded(const SceneDev& s, int l, float4 q, con
   } else if (!kPrefilter) {
     // every reversed shadow ray starts at the light: o - c and r^2 from the
     // scene's table
+    uint64_t open = wave_mask(!occ);
     scan_spheres(
         ocs, s.n4,
         [&](int i, float4 a) {
           cnt.exec((occ || i >= s.n_spheres) ? 0 : 1, 0);   // padding spheres are no work
-          shadow_sphere_oc(a.x, a.y, a.z, a.w, i, rr, lim, self, occ, first);
+          shadow_sphere_open(a.x, a.y, a.z, a.w, i, rr, lim, self, occ, first, open);
         },
-        [&] { return !wave_any(!occ); });   // every lane of the wave is occluded
+        [&] { return open == 0; });   // every lane of the wave is occluded
   } else {
     scan_spheres(
         cones, s.n4,
