@@ -272,6 +272,21 @@ __device__ __forceinline__ bool wave_any(bool p) { return __builtin_amdgcn_ballo
 __device__ __forceinline__ uint64_t wave_mask(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 __device__ __forceinline__ bool wave_full() { return __builtin_amdgcn_read_exec() == ~0ull; }
 
+// The value v of the lanes with `take` when they all hold the same one, else
+// -1 (also when no lane takes part).
+__device__ __forceinline__ int wave_common(bool take, int v) {
+  const uint64_t m = wave_mask(take);
+  if (!m) return -1;
+  const int v0 = __builtin_amdgcn_readlane(v, (int)__builtin_ctzll(m));
+  return wave_any(take & (v != v0)) ? -1 : v0;
+}
+// Bit of primitive `id` in the 64-sphere chunk starting at `base` (0 when it
+// lies outside the chunk or id < 0).
+__device__ __forceinline__ uint64_t chunk_bit(int id, int base) {
+  const unsigned k = (unsigned)(id - base);
+  return k < 64u ? (1ull << k) : 0ull;
+}
+
 __device__ __forceinline__ float lane_read(float v, int lane) {
   return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
 }
@@ -1157,6 +1172,10 @@ __device__ __forceinline__ float soft_visibility(const SceneDev& s, float4 q, co
   float ax, ay, az, bx, by, bz;
   perp_basis(lx, ly, lz, ax, ay, az, bx, by, bz);
   const int self = f.id;
+  // the surface every participating lane leaves, when it is the same for all
+  // of them: it always passes the bound (the bundle's rays start on it) but
+  // no sample ray tests it, so the candidate masks drop it
+  const int wself = kPrefilter ? wave_common(act, self) : -1;
   const float tmin = s.t_min;
   uint64_t cand[kSoftChunks];
 #pragma unroll
@@ -1181,7 +1200,8 @@ __device__ __forceinline__ float soft_visibility(const SceneDev& s, float4 q, co
           if (64 * c < s.n_spheres) {
             const int j = 64 * c + lane;
             const int jc = j < s.n_spheres ? j : s.n_spheres - 1;
-            cand[c] = wave_mask((j < s.n_spheres) & sphere_may_meet(wb, s.geom[jc], s.rad[jc].x));
+            cand[c] = wave_mask((j < s.n_spheres) & sphere_may_meet(wb, s.geom[jc], s.rad[jc].x)) &
+                      ~chunk_bit(wself, 64 * c);
           }
         }
         culled = true;
