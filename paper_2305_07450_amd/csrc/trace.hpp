@@ -1208,6 +1208,34 @@ __device__ __forceinline__ float soft_visibility(const SceneDev& s, float4 q, co
       }
     }
   }
+  // Planes that no sample ray of the wave can reach (bit j).  Every lane
+  // taking part and not lying on plane j has its p above the plane by more
+  // than 1e-4 of the terms of its plane equation and 1e-5 of its farthest
+  // sample (num = h - m.p < 0 beyond its rounding), and the whole light disk
+  // lies above the plane by more than 2 % of the highest such p plus 1e-5 of
+  // the farthest sample.  A sample ray's segment from p to its sample point
+  // then stays above the plane: descending, it would meet the plane beyond
+  // the point, and these margins keep the computed root above the computed
+  // distance through the FP32 error of num, den, the root and the distance;
+  // ascending, the computed root is negative.  Either way the test reports
+  // no block, so skipping it changes no bit.
+  uint32_t far_planes = 0;
+  if (kPrefilter) {
+    const float reach = dist + 2.0001f * sh.radius;   // farthest sample from p
+    for (int j = 0; j < s.n_planes && j < 32; ++j) {
+      const float4 pg = ld4(s.pgeom, j);
+      const float mn = fsqrt(dot3(pg.x, pg.y, pg.z, pg.x, pg.y, pg.z));
+      const float num = pg.w - dot3(pg.x, pg.y, pg.z, f.px, f.py, f.pz);
+      const float terms = fabsf(pg.x * f.px) + fabsf(pg.y * f.py) + fabsf(pg.z * f.pz) + fabsf(pg.w);
+      const bool mine = act & (s.n_spheres + j != self);
+      const bool clear = -num > fmaf(1e-4f, terms, 1e-5f * reach * mn);
+      const float high = -wave_min(mine ? num : 0.0f);            // highest p
+      const float farthest = -wave_min(mine ? -reach : 0.0f);     // farthest sample
+      const float low = dot3(pg.x, pg.y, pg.z, q.x, q.y, q.z) - pg.w - 2.0001f * sh.radius * mn;
+      if (!wave_any(mine & !clear) && low > fmaf(0.02f, high, 1e-5f * farthest * mn))
+        far_planes |= 1u << j;
+    }
+  }
   int visible = 0;
   // the light centre relative to p, formed once: a sample ray's direction is
   // q - p plus the sample's offset in the disk
@@ -1256,6 +1284,7 @@ __device__ __forceinline__ float soft_visibility(const SceneDev& s, float4 q, co
               [&] { return !wave_any(any_open(blk)); });
         }
         for (int j = 0; j < s.n_planes; ++j) {
+          if (j < 32 && ((far_planes >> j) & 1u)) continue;
           const float4 pg = ld4(s.pgeom, j);
           const bool other = s.n_spheres + j != self;
           // plane_root with the origin term, the same for every sample ray of

@@ -87,6 +87,40 @@ def test_soft_bounds_change_no_bits(rt, case):
     assert np.array_equal(a["rgb"], b["rgb"]) and np.array_equal(a["ids"], b["ids"])
 
 
+def _unit(v):
+    v = np.asarray(v, dtype=np.float64)
+    return v / np.linalg.norm(v)
+
+
+# Planes that the sample rays of whole waves can be shown not to reach are not
+# tested for them; these scenes put lights, spheres and planes near the edges
+# of that proof: lights just above or below the floor, spheres through it,
+# a wall behind the spheres and a tilted plane.
+PLANE_CASES = [
+    ("low lights", ((-4.0, -1.5, -12.0), (4.0, 1.0, -4.0)), ((-5.0, -0.95, -10.0), (5.0, -0.2, -2.0)),
+     scenegen.GROUND),
+    ("floor and wall", scenegen.BOX_SMALL, scenegen.LIGHT_BOX,
+     np.array([[0.0, 1.0, 0.0, -1.0], [0.0, 0.0, 1.0, -14.0]], dtype=np.float32)),
+    ("tilted plane", scenegen.BOX_SMALL, scenegen.LIGHT_BOX,
+     np.array([[*_unit([0.3, 0.9, 0.1]), -1.5]], dtype=np.float32)),
+    ("lights under the floor", scenegen.BOX_SMALL, ((-5.0, -4.0, -10.0), (5.0, -1.2, -2.0)),
+     scenegen.GROUND),
+]
+
+
+@pytest.mark.parametrize("case", range(len(PLANE_CASES)))
+def test_soft_plane_skip_changes_no_bits(rt, case):
+    label, box, light_box, planes = PLANE_CASES[case]
+    s = scenegen.random_scene(np.random.default_rng(930 + case), 24, 2, box=box,
+                              light_box=light_box, planes=planes)
+    cam = Camera(pitch_deg=-6.0)
+    W, H, D, n, R = 112, 64, 3, 64, 0.8
+    log("case soft plane skip", label, W, H, D, n, R)
+    a = soft_render(rt, s, cam, W, H, D, n, R, 0)
+    b = soft_render(rt, s, cam, W, H, D, n, R, rt.RT_RENDER_NO_PREFILTER)
+    assert np.array_equal(a["rgb"], b["rgb"]) and np.array_equal(a["ids"], b["ids"]), label
+
+
 def test_one_sample_or_radius_zero_is_point_light(rt):
     s = scenegen.tiny_scene(71, n_spheres=20, n_lights=2)
     cam = Camera(pitch_deg=-5.0)
