@@ -1115,8 +1115,9 @@ constexpr int kSoftGroup = 8;
 
 // Exact test of one sphere against a group of sample rays of the lanes, for
 // the rays not yet blocked: a root in (t_min, dist) of a sphere other than
-// the surface.  The arithmetic per ray is sphere_ff's.
-__device__ __forceinline__ void soft_blockers(float4 g, int i, const Surface& f, const float* dx,
+// the surface.  The arithmetic per ray is sphere_ff's.  Returns whether the
+// wave took the roots (the only case in which a ray can become blocked).
+__device__ __forceinline__ bool soft_blockers(float4 g, int i, const Surface& f, const float* dx,
                                               const float* dy, const float* dz,
                                               const float* dist, float tmin, int self,
                                               bool* blk) {
@@ -1141,14 +1142,16 @@ __device__ __forceinline__ void soft_blockers(float4 g, int i, const Surface& f,
       const float t0 = -b[k] - sq, t1 = -b[k] + sq;
       blk[k] = blk[k] | (in[k] & (((t0 > tmin) & (t0 < dist[k])) | ((t1 > tmin) & (t1 < dist[k]))));
     }
+    return true;
   }
+  return false;
 }
 
 __device__ __forceinline__ bool any_open(const bool* blk) {
-  bool o = false;
+  bool all = true;
 #pragma unroll
-  for (int k = 0; k < kSoftGroup; ++k) o |= !blk[k];
-  return o;
+  for (int k = 0; k < kSoftGroup; ++k) all &= blk[k];
+  return !all;
 }
 
 // Share of light l's sample points whose shadow rays from the hit point p
@@ -1272,9 +1275,11 @@ __device__ __forceinline__ float soft_visibility(const SceneDev& s, float4 q, co
             while (m) {
               const int k = (int)__builtin_ctzll(m);
               m &= m - 1;
-              soft_blockers(ld4(s.geom, 64 * c + k), 64 * c + k, f, dx, dy, dz, di, tmin, self,
-                            blk);
-              if (!wave_any(any_open(blk))) m = 0;
+              // the samples' state changes only where the roots were taken
+              if (soft_blockers(ld4(s.geom, 64 * c + k), 64 * c + k, f, dx, dy, dz, di, tmin,
+                                self, blk) &&
+                  !wave_any(any_open(blk)))
+                m = 0;
             }
           }
         } else {
