@@ -1243,6 +1243,24 @@ __device__ __forceinline__ float soft_visibility(const SceneDev& s, float4 q, co
   // the light centre relative to p, formed once: a sample ray's direction is
   // q - p plus the sample's offset in the disk
   const float qpx = q.x - f.px, qpy = q.y - f.py, qpz = q.z - f.pz;
+  if (kPrefilter && culled && s.n_planes <= 32) {
+    // Every sample of every participating lane is visible when no sphere is
+    // a candidate, no plane is in reach, and each lane has the whole light
+    // disk in front of its tangent plane by more than 1e-5 of its farthest
+    // sample: the offset of a sample from q is at most 2R (the table holds
+    // R times points of the disk of radius 2), so n.x > 0 for every sample
+    // vector x by a margin far above the FP32 error of x, its normalisation
+    // and n.d.  The sample loop would then count all n samples, and n / n is
+    // exactly 1.
+    uint64_t any = 0;
+#pragma unroll
+    for (int c = 0; c < kSoftChunks; ++c) any |= cand[c];
+    const uint32_t planes = s.n_planes == 32 ? ~0u : (1u << s.n_planes) - 1u;
+    if (any == 0 && (far_planes & planes) == planes &&
+        !wave_any(act & !(dot3(f.nx, f.ny, f.nz, qpx, qpy, qpz) >
+                          fmaf(2.0001f, sh.radius, 1e-5f * (dist + 2.0001f * sh.radius)))))
+      return act ? 1.0f : 0.0f;
+  }
   // the table is read 8 samples (64 bytes) per scalar load; it holds a
   // multiple of 8 entries, so the last block stays inside it (entries past n
   // are read but count as blocked)
