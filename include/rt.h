@@ -252,6 +252,11 @@ rt_status rt_render_prepare(rt_scene scene, const rt_camera* cam, int32_t W, int
  *   rgb_out, id_out as rt_render_ex; flags RT_RENDER_NO_PREFILTER and
  *   RT_RENDER_ROW_ORDER.  No records: the adjoint and the batched launch take
  *   point lights.
+ * Without RT_RENDER_NO_PREFILTER a wave skips only tests whose outcome it has
+ * shown, with FP32 error margins: spheres outside its bound, the sphere all
+ * its lanes lie on, planes its sample rays cannot reach, and the whole sample
+ * loop when every sample is visible; the image is the same bits as with the
+ * flag, which tests every sample ray against every primitive.
  * Launches three kernels (the preparation as rt_render's, the sample table,
  * the render): like rt_render it records every tile's duration and takes the
  * tiles longest first by the record of the last soft-shadow render of the
