@@ -258,7 +258,9 @@ rt_status rt_render_prepare(rt_scene scene, const rt_camera* cam, int32_t W, int
  * loop when every sample is visible; the image is the same bits as with the
  * flag, which tests every sample ray against every primitive.
  * Launches three kernels (the preparation as rt_render's, the sample table,
- * the render): like rt_render it records every tile's duration and takes the
+ * the render; images of up to 40 000 8 x 8 tiles share each pixel's samples
+ * between two lanes, whose integer counts are added): like rt_render it
+ * records every tile's duration and takes the
  * tiles longest first by the record of the last soft-shadow render of the
  * scene at this W x H (hard- and soft-shadow renders keep apart records; an
  * image takes the same bits in any order).  No allocation, capture-safe.

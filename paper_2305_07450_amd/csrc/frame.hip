@@ -176,7 +176,7 @@ void fill_args(const rt_frame_s* f, const rt_camera& cam, int depth, int samples
   a.prep_p.kernelParams = a.prep_args;
   const bool sky = sc.sky != nullptr;
   a.render_p.gridDim = render_grid(f->W, f->H);
-  a.render_p.blockDim = dim3(kRenderThreads);
+  a.render_p.blockDim = dim3(f->soft ? kRenderThreads * soft_parts(f->W, f->H) : kRenderThreads);
   if (f->soft) {
     a.samples = samples;
     a.radius = radius;
@@ -191,6 +191,7 @@ void fill_args(const rt_frame_s* f, const rt_camera& cam, int depth, int samples
     a.sh.n = samples;
     a.sh.radius = radius;
     a.sh.table = sc.soft_table;
+    a.sh.parts = soft_parts(f->W, f->H);
     // render_soft_kernel(SceneDev, CameraDev, int depth, SoftShadows, float* rgb, int32_t* ids)
     a.render_args[0] = &a.s;
     a.render_args[1] = &a.c;

@@ -109,19 +109,26 @@ __attribute__((amdgpu_waves_per_eu(kRecords ? 6 : 1))) void render_kernel(SceneD
 
 // Soft-shadow render: the same paths with every light sampled (SoftShadows).
 template <bool kPrefilter, class Bg>
-__global__ __launch_bounds__(kRenderThreads, 4) void render_soft_kernel(SceneDev s, CameraDev c, int depth,
-                                                           SoftShadows sh,
-                                                           float* __restrict__ rgb,
-                                                           int32_t* __restrict__ id_out) {
-  const int lane = threadIdx.x;
+// Launched with sh.parts waves per tile: the tile's 64 pixels are spread
+// over them, sh.parts neighbouring lanes a pixel, each taking its share of
+// the samples (soft_visibility adds their counts).
+__global__ __launch_bounds__(kSoftMaxThreads) __attribute__((amdgpu_waves_per_eu(4))) void render_soft_kernel(
+    SceneDev s, CameraDev c, int depth, SoftShadows sh, float* __restrict__ rgb,
+    int32_t* __restrict__ id_out) {
+  const int wave = (int)threadIdx.x >> 6;
+  const int lane = (int)threadIdx.x & 63;
   // the tile: row order, or the scene's order (as render_kernel)
   const int t = tile_of(s);
   const int ty = t / (int)gridDim.x;
   const int tx = t - ty * (int)gridDim.x;
+  const int px = wave * (64 / sh.parts) + lane / sh.parts;   // pixel of the tile
+  sh.part = lane % sh.parts;
+  // the first wave measures the tile for the next render's order (the waves
+  // share no data, and none waits for another)
   __shared__ uint64_t s_start;
-  if (s.sched_mode & kSchedRecord) s_start = __builtin_amdgcn_s_memtime();
-  const int x = tx * kTile + (lane & 7);
-  const int y = ty * kTile + (lane >> 3);
+  if ((s.sched_mode & kSchedRecord) && wave == 0) s_start = __builtin_amdgcn_s_memtime();
+  const int x = tx * kTile + (px & 7);
+  const int y = ty * kTile + (px >> 3);
   const bool live = x < c.W && y < c.H;
   if (!wave_any(live)) return;
   const int64_t pix = live ? (int64_t)y * c.W + x : 0;
@@ -132,13 +139,13 @@ __global__ __launch_bounds__(kRenderThreads, 4) void render_soft_kernel(SceneDev
   // no LDS ray slots: they cost the skybox variant a wave per SIMD (129 VGPRs)
   trace_path<NoRecords, NoCount, kPrefilter, SoftShadows, Bg, false>(s, r, depth, live, cr, cg, cb,
                                                                        prim, sink, NoCount(), sh);
-  if (live) {
+  if (live && sh.part == 0) {
     rgb[3 * pix + 0] = cr;
     rgb[3 * pix + 1] = cg;
     rgb[3 * pix + 2] = cb;
     if (id_out) id_out[pix] = prim;
   }
-  if (s.sched_mode & kSchedRecord) record_duration(s, tile_of(s), s_start);
+  if ((s.sched_mode & kSchedRecord) && wave == 0) record_duration(s, tile_of(s), s_start);
 }
 
 // Sample points of the sunflower arrangement: point i of n at radius
@@ -166,6 +173,7 @@ hipError_t launch_render_soft(const rt_scene_s& sc, const CameraDev& c, int dept
   sh.n = samples;
   sh.radius = radius;
   sh.table = sc.soft_table;
+  sh.parts = soft_parts(c.W, c.H);
   const dim3 grid = render_grid(c.W, c.H);
   const bool sky = sc.sky != nullptr;
   auto kern = sky ? (prefilter ? render_soft_kernel<true, SkyBackground>
@@ -174,7 +182,8 @@ hipError_t launch_render_soft(const rt_scene_s& sc, const CameraDev& c, int dept
                                : render_soft_kernel<false, PlainBackground>);
   SceneDev s = sc.view();
   s.sched_mode = sched_mode;
-  hipLaunchKernelGGL(kern, grid, dim3(kRenderThreads), 0, stream, s, c, depth, sh, rgb, ids);
+  hipLaunchKernelGGL(kern, grid, dim3(kRenderThreads * sh.parts), 0, stream, s, c, depth, sh, rgb,
+                     ids);
   return hipGetLastError();
 }
 

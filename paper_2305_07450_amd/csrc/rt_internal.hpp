@@ -65,11 +65,22 @@ struct rt_scene_s {
 
 namespace rtk {
 
-// Render launches: one wave per workgroup, an 8 x 8 pixel tile per wave.
+// Render launches: one wave per workgroup, an 8 x 8 pixel tile per wave (the
+// soft-shadow render of smaller images: two waves per tile, below).
 constexpr int kRenderTile = 8;
 constexpr int kRenderThreads = 64;
+// Soft-shadow renders of images up to kSoftSplitMaxTiles tiles share each
+// pixel's samples between two neighbouring lanes (two waves per tile): such
+// frames are set by the latency of their slowest tiles, which this halves;
+// larger images are set by throughput, which the shared paths would cost.
+constexpr int kSoftSplitMaxTiles = 40000;
+constexpr int kSoftMaxThreads = 2 * kRenderThreads;
 inline dim3 render_grid(int W, int H) {
   return dim3((W + kRenderTile - 1) / kRenderTile, (H + kRenderTile - 1) / kRenderTile);
+}
+inline int soft_parts(int W, int H) {
+  const dim3 g = render_grid(W, H);
+  return (int64_t)g.x * g.y <= kSoftSplitMaxTiles ? 2 : 1;
 }
 
 // Tile scheduling of the hard-shadow render (schedule.hip): images of at

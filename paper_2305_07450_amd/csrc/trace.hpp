@@ -1087,6 +1087,10 @@ struct SoftShadows {
   const float2* table;  // [n, rounded up to 8]: sample i in the disk basis,
                         // R times the FP32 rounding of 2 sqrt(i/n) (cos(i phi),
                         // sin(i phi)), phi the golden angle; 64-byte aligned
+  int parts = 1;        // lanes sharing a pixel's samples: 1, 2 or 4, the
+                        // neighbouring lanes of an aligned group
+  int part = 0;         // this lane's share: the blocks of 8 samples b with
+                        // b % parts == part (set per lane by the kernel)
 };
 
 // Chunks of 64 spheres whose candidate masks a soft-shadow bound keeps; a
@@ -1265,11 +1269,19 @@ __device__ __forceinline__ float soft_visibility(const SceneDev& s, float4 q, co
   // multiple of 8 entries, so the last block stays inside it (entries past n
   // are read but count as blocked)
   static_assert(8 % kSoftGroup == 0, "sample groups split a table block");
-  for (int i0 = 0; i0 < sh.n; i0 += 8) {
-    const rt_v16 tb = ((const RT_CONSTANT rt_v16*)sh.table)[i0 >> 3];
+  const int last_block = (sh.n - 1) >> 3;
+  for (int j0 = 0; j0 < sh.n; j0 += 8 * sh.parts) {
+    // this lane's block of 8 samples: with one lane a pixel the same for the
+    // whole wave (a scalar load); otherwise the lanes of a pixel read
+    // different blocks, and past the last block a lane reads the last one
+    // and counts its samples as blocked
+    const int blk = (j0 >> 3) + sh.part;
+    const int i0 = 8 * blk;
+    const rt_v16 tb = sh.parts == 1 ? ((const RT_CONSTANT rt_v16*)sh.table)[j0 >> 3]
+                                    : ((const rt_v16*)sh.table)[min(blk, last_block)];
 #pragma unroll
     for (int k0 = 0; k0 < 8; k0 += kSoftGroup) {
-      if (i0 + k0 >= sh.n) break;
+      if (j0 + k0 >= sh.n) break;
       float dx[kSoftGroup], dy[kSoftGroup], dz[kSoftGroup], di[kSoftGroup];
       bool blk[kSoftGroup];
 #pragma unroll
@@ -1325,6 +1337,10 @@ __device__ __forceinline__ float soft_visibility(const SceneDev& s, float4 q, co
       for (int k = 0; k < kSoftGroup; ++k) visible += blk[k] ? 0 : 1;
     }
   }
+  // the counts of the lanes that share the pixel: integer sums, the same in
+  // any order
+  if (sh.parts >= 2) visible += __builtin_amdgcn_mov_dpp(visible, 0xB1, 0xf, 0xf, true);
+  if (sh.parts >= 4) visible += __builtin_amdgcn_mov_dpp(visible, 0x4E, 0xf, 0xf, true);
   return act ? (float)visible / (float)sh.n : 0.0f;
 }
 

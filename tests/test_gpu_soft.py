@@ -121,6 +121,20 @@ def test_soft_plane_skip_changes_no_bits(rt, case):
     assert np.array_equal(a["rgb"], b["rgb"]) and np.array_equal(a["ids"], b["ids"]), label
 
 
+# Images of up to 40 000 tiles share each pixel's samples between two lanes;
+# larger ones give each pixel one lane.  Both sides of that limit, with and
+# without the bounds and skips (the same bits either way).
+@pytest.mark.parametrize("W,H", [(1600, 1600), (1608, 1600)])
+def test_soft_lanes_per_pixel_limit_changes_no_bits(rt, W, H):
+    s = scenegen.paper_scene()
+    cam = Camera(yaw_deg=4.0, pitch_deg=-2.0)
+    D, n, R = 2, 24, scenegen.PAPER_LIGHT_RADIUS
+    log("case soft lanes per pixel", W, H, D, n, R)
+    a = soft_render(rt, s, cam, W, H, D, n, R, 0)
+    b = soft_render(rt, s, cam, W, H, D, n, R, rt.RT_RENDER_NO_PREFILTER)
+    assert np.array_equal(a["rgb"], b["rgb"]) and np.array_equal(a["ids"], b["ids"])
+
+
 def test_one_sample_or_radius_zero_is_point_light(rt):
     s = scenegen.tiny_scene(71, n_spheres=20, n_lights=2)
     cam = Camera(pitch_deg=-5.0)
