@@ -1172,6 +1172,11 @@ __device__ __forceinline__ bool any_open(const bool* blk) {
 // lane's w, so the wave bundle of the hit points and light directions, with
 // its cone widened by the largest alpha (less 2e-6 in cos for rounding), holds
 // every sample ray, and only the spheres it may meet are tested.
+//
+// With sh.parts > 1 the sh.parts neighbouring lanes of a pixel (same path,
+// same p) each count their share of the blocks of 8 samples, and the counts
+// are added across those lanes before the division, so every split gives the
+// same share.
 template <bool kPrefilter>
 __device__ __forceinline__ float soft_visibility(const SceneDev& s, float4 q, const Surface& f,
                                                  float lx, float ly, float lz, float dist,
