@@ -108,10 +108,10 @@ __attribute__((amdgpu_waves_per_eu(kRecords ? 6 : 1))) void render_kernel(SceneD
 }
 
 // Soft-shadow render: the same paths with every light sampled (SoftShadows).
-template <bool kPrefilter, class Bg>
 // Launched with sh.parts waves per tile: the tile's 64 pixels are spread
 // over them, sh.parts neighbouring lanes a pixel, each taking its share of
 // the samples (soft_visibility adds their counts).
+template <bool kPrefilter, class Bg>
 __global__ __launch_bounds__(kSoftMaxThreads) __attribute__((amdgpu_waves_per_eu(4))) void render_soft_kernel(
     SceneDev s, CameraDev c, int depth, SoftShadows sh, float* __restrict__ rgb,
     int32_t* __restrict__ id_out) {
