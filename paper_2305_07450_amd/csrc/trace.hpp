@@ -1252,6 +1252,13 @@ __device__ __forceinline__ float soft_visibility(const SceneDev& s, float4 q, co
   // the light centre relative to p, formed once: a sample ray's direction is
   // q - p plus the sample's offset in the disk
   const float qpx = q.x - f.px, qpy = q.y - f.py, qpz = q.z - f.pz;
+  // every participating lane has the whole light disk in front of its tangent
+  // plane by more than 1e-5 of its farthest sample (below): no sample is
+  // behind that plane, and the per-sample test is skipped
+  const bool all_front =
+      kPrefilter &&
+      !wave_any(act & !(dot3(f.nx, f.ny, f.nz, qpx, qpy, qpz) >
+                        fmaf(2.0001f, sh.radius, 1e-5f * (dist + 2.0001f * sh.radius))));
   if (kPrefilter && culled && s.n_planes <= 32) {
     // Every sample of every participating lane is visible when no sphere is
     // a candidate, no plane is in reach, and each lane has the whole light
@@ -1265,10 +1272,7 @@ __device__ __forceinline__ float soft_visibility(const SceneDev& s, float4 q, co
 #pragma unroll
     for (int c = 0; c < kSoftChunks; ++c) any |= cand[c];
     const uint32_t planes = s.n_planes == 32 ? ~0u : (1u << s.n_planes) - 1u;
-    if (any == 0 && (far_planes & planes) == planes &&
-        !wave_any(act & !(dot3(f.nx, f.ny, f.nz, qpx, qpy, qpz) >
-                          fmaf(2.0001f, sh.radius, 1e-5f * (dist + 2.0001f * sh.radius)))))
-      return act ? 1.0f : 0.0f;
+    if (any == 0 && (far_planes & planes) == planes && all_front) return act ? 1.0f : 0.0f;
   }
   // the table is read 8 samples (64 bytes) per scalar load; it holds a
   // multiple of 8 entries, so the last block stays inside it (entries past n
@@ -1300,7 +1304,12 @@ __device__ __forceinline__ float soft_visibility(const SceneDev& s, float4 q, co
         const float inv = frsq(d2);
         di[k] = d2 * inv;
         dx[k] = x * inv; dy[k] = y * inv; dz[k] = z * inv;
-        blk[k] = (i0 + kk >= sh.n) | !act | !(dot3(f.nx, f.ny, f.nz, dx[k], dy[k], dz[k]) > 0.0f);
+        blk[k] = (i0 + kk >= sh.n) | !act;
+      }
+      if (!all_front) {
+#pragma unroll
+        for (int k = 0; k < kSoftGroup; ++k)
+          blk[k] = blk[k] | !(dot3(f.nx, f.ny, f.nz, dx[k], dy[k], dz[k]) > 0.0f);
       }
       if (wave_any(any_open(blk))) {
         if (culled) {
